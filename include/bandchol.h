@@ -1,0 +1,101 @@
+/*
+ * bandchol: FP64 Cholesky factorization of symmetric positive-definite band
+ * matrices and the band solves that use the factor, on AMD MI355X (gfx950).
+ *
+ * Method: A = L L^T with L lower triangular, positive diagonal, and the lower
+ * bandwidth k of A.  The factor is unique (Section 2 of Liu, Fredriksson and
+ * Markidis, "Parallel Cholesky Factorization for Banded Matrices using
+ * OpenMP Tasks", arXiv 2305.04635).  The GPU walks the band in square tiles:
+ * each diagonal tile is factored (dense Cholesky), the tiles below it are
+ * solved against it (triangular solve), and the tiles further right receive
+ * the rank-nb updates (the potrf / trsm / gemm / syrk steps of Algorithm 1,
+ * Section 3).  Flop count used for rates: n(k^2 + 3k) (Section 3.2).
+ *
+ * Storage (all routines): LAPACK lower band layout, column-major,
+ *   A(i, j) for 0 <= i - j <= k  at  ab[(i - j) + j * ldab],  ldab >= k + 1
+ * (the paper keeps the standard LAPACK band format, Sections 3 and 6).  Rows
+ * k+1 .. ldab-1 of every column and the positions past row n-1 in the last k
+ * columns are never read or written.  Indices are 0-based; info is 1-based.
+ *
+ * Pointers: every array argument is a DEVICE pointer on the current HIP
+ * device, allocated and owned by the caller.  The library never frees caller
+ * memory.  It owns one workspace per device (grown on demand with hipMalloc,
+ * released by bandchol_finalize); a call that needs a larger workspace than
+ * the one held must therefore not run under stream capture.
+ *
+ * Streams: the synchronous calls run on the stream set with
+ * bandchol_set_stream for the calling thread (default: the null stream) and
+ * wait for it.  The _async calls run on the stream passed in and do not wait.
+ *
+ * Errors: 0 = success; -i = the i-th argument is illegal (checked before any
+ * GPU work); BANDCHOL_EHIP = a HIP runtime error (bandchol_last_error() gives
+ * its text); BANDCHOL_EHANG = a device-side wait exceeded its bound (the
+ * kernel exited instead of hanging; results unspecified).
+ *
+ * Inputs must be finite except for NaN, which is reported: a NaN anywhere in
+ * the band makes info point at the first pivot it reaches.
+ */
+#ifndef BANDCHOL_H
+#define BANDCHOL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BANDCHOL_EHIP (-1000)
+#define BANDCHOL_EHANG (-1001)
+
+/*
+ * Factor A = L L^T in place (LAPACK pbtrf, uplo = 'L').
+ *   n     order of A, n >= 0                                   (bad: -1)
+ *   k     number of sub-diagonals, k >= 0; k >= n-1 is the dense case (bad: -2)
+ *   ab    device pointer to the band, ldab x n column-major    (NULL with n > 0: -3)
+ *   ldab  leading dimension, ldab >= k + 1                     (bad: -4)
+ * Returns 0 on success, < 0 on a bad argument or runtime error, or info > 0:
+ * the 1-based index of the first column whose pivot A(j,j) - sum_l L(j,l)^2
+ * is not positive (zero, negative or NaN), i.e. the leading minor of that
+ * order is not positive definite.  After info > 0 the contents of ab are
+ * unspecified.  Synchronous: waits for the stream and reads info back.
+ */
+int64_t bandchol_factor(int64_t n, int64_t k, double* ab, int64_t ldab);
+
+/*
+ * Solve A X = B with the factor from bandchol_factor (LAPACK pbtrs, uplo =
+ * 'L'): forward L Y = B, then back L^T X = Y.
+ *   n -1, k -2, nrhs >= 0 -3, ab (factor) -4, ldab >= k+1 -5,
+ *   b device pointer, n x nrhs column-major -6, ldb >= max(1, n) -7.
+ * B is overwritten by X.  The factor is not inspected for zero pivots: call
+ * only after bandchol_factor returned 0.  Synchronous.
+ */
+int64_t bandchol_solve(int64_t n, int64_t k, int64_t nrhs, const double* ab, int64_t ldab, double* b,
+                       int64_t ldb);
+
+/*
+ * Stream-ordered forms.  No host synchronisation.  bandchol_factor_async
+ * writes info (as above; 0 on success) to *d_info, a device int64.  Argument
+ * codes are returned immediately.  stream is a hipStream_t (NULL = null stream).
+ */
+int64_t bandchol_factor_async(int64_t n, int64_t k, double* ab, int64_t ldab, int64_t* d_info,
+                              void* stream);
+int64_t bandchol_solve_async(int64_t n, int64_t k, int64_t nrhs, const double* ab, int64_t ldab,
+                             double* b, int64_t ldb, void* stream);
+
+/* Stream used by the synchronous calls of the calling thread (hipStream_t). */
+int64_t bandchol_set_stream(void* stream);
+
+/* Text of the last error in the calling thread ("" if none). */
+const char* bandchol_last_error(void);
+
+/* Release the per-device workspaces. */
+void bandchol_finalize(void);
+
+/* Tile width the factor uses (the rank of each trailing update). */
+int64_t bandchol_tile(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BANDCHOL_H */

@@ -1,0 +1,133 @@
+"""MI355X (gfx950) FP64 band Cholesky factor and band solves.
+
+Thin ctypes binding over ``libbandchol.so`` (C-ABI in ``include/bandchol.h``).
+Every function takes float64 GPU tensors and passes their device pointers and
+the current torch stream; all arithmetic runs in the library's HIP kernels.
+There is no fallback: if the library is missing or no GPU is present the calls
+raise.
+
+Band storage is LAPACK lower band, column-major: ``A(i, j)`` for
+``0 <= i - j <= k`` at flat index ``(i - j) + j * ldab``.  A tensor of shape
+``(n, ldab)`` (row ``j`` = band column ``j``) has exactly this memory layout.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbandchol.so")
+_lib = None
+
+_I64 = ctypes.c_int64
+_VP = ctypes.c_void_p
+
+# name -> (restype, argtypes); the exported C-ABI, as declared in include/bandchol.h
+SIGNATURES = {
+    "bandchol_factor": (_I64, [_I64, _I64, _VP, _I64]),
+    "bandchol_solve": (_I64, [_I64, _I64, _I64, _VP, _I64, _VP, _I64]),
+    "bandchol_factor_async": (_I64, [_I64, _I64, _VP, _I64, _VP, _VP]),
+    "bandchol_solve_async": (_I64, [_I64, _I64, _I64, _VP, _I64, _VP, _I64, _VP]),
+    "bandchol_set_stream": (_I64, [_VP]),
+    "bandchol_last_error": (ctypes.c_char_p, []),
+    "bandchol_finalize": (None, []),
+    "bandchol_tile": (_I64, []),
+}
+
+EHIP = -1000
+EHANG = -1001
+
+
+class BandCholError(RuntimeError):
+    pass
+
+
+def load(path=LIB_PATH):
+    """Load the HIP library (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise BandCholError("libbandchol.so is not built (run paper_2305_04635_amd.build.build())")
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check_tensor(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError("%s must be a float64 GPU tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _raise(rc, what):
+    msg = load().bandchol_last_error().decode(errors="replace")
+    raise BandCholError("%s failed (%d): %s" % (what, rc, msg))
+
+
+def tile():
+    return int(load().bandchol_tile())
+
+
+def factor(ab, n, k, ldab=None):
+    """Factor the band in ``ab`` in place (A = L L^T); returns info (0 = success)."""
+    ldab = k + 1 if ldab is None else ldab
+    _check_tensor(ab, "ab")
+    if ab.numel() < ldab * n:
+        raise ValueError("ab holds fewer than ldab*n elements")
+    lib = load()
+    lib.bandchol_set_stream(_stream())
+    rc = lib.bandchol_factor(n, k, ab.data_ptr(), ldab)
+    if rc < 0:
+        _raise(rc, "bandchol_factor")
+    return int(rc)
+
+
+def factor_async(ab, n, k, d_info, ldab=None):
+    """Stream-ordered factor; writes info to the int64 GPU tensor d_info."""
+    import torch
+    ldab = k + 1 if ldab is None else ldab
+    _check_tensor(ab, "ab")
+    if d_info.dtype != torch.int64 or not d_info.is_cuda:
+        raise TypeError("d_info must be an int64 GPU tensor")
+    rc = load().bandchol_factor_async(n, k, ab.data_ptr(), ldab, d_info.data_ptr(), _stream())
+    if rc != 0:
+        _raise(rc, "bandchol_factor_async")
+
+
+def solve(ab, n, k, b, nrhs=None, ldab=None, ldb=None):
+    """Solve A X = B in place in ``b`` (n x nrhs column-major) with the factor in ``ab``."""
+    ldab = k + 1 if ldab is None else ldab
+    _check_tensor(ab, "ab")
+    _check_tensor(b, "b")
+    nrhs = (b.numel() // max(n, 1)) if nrhs is None else nrhs
+    ldb = max(n, 1) if ldb is None else ldb
+    lib = load()
+    lib.bandchol_set_stream(_stream())
+    rc = lib.bandchol_solve(n, k, nrhs, ab.data_ptr(), ldab, b.data_ptr(), ldb)
+    if rc != 0:
+        _raise(rc, "bandchol_solve")
+
+
+def solve_async(ab, n, k, b, nrhs=None, ldab=None, ldb=None):
+    ldab = k + 1 if ldab is None else ldab
+    _check_tensor(ab, "ab")
+    _check_tensor(b, "b")
+    nrhs = (b.numel() // max(n, 1)) if nrhs is None else nrhs
+    ldb = max(n, 1) if ldb is None else ldb
+    rc = load().bandchol_solve_async(n, k, nrhs, ab.data_ptr(), ldab, b.data_ptr(), ldb, _stream())
+    if rc != 0:
+        _raise(rc, "bandchol_solve_async")
+
+
+def finalize():
+    if _lib is not None:
+        _lib.bandchol_finalize()

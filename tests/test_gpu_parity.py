@@ -1,0 +1,129 @@
+"""GPU parity: the HIP factor and solves against the CPU oracle, through the C-ABI.
+
+Bars (FP64): relative backward error ||L L^T - A||_F / ||A||_F <= 1e-12 and
+solve residual ||b - A x||_inf / (||A||_inf ||x||_inf) <= 1e-12; the forward
+error of x against the oracle's x within 1e-12 * kappa_1(A) (Hager/Higham
+estimate); elementwise L against the oracle's L within a kappa-free bound for
+the diagonally dominant matrices; bit-exact where the arithmetic is exact.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import ETA_TOL, U, gpu_factor, gpu_solve, rel_fro
+
+pytestmark = pytest.mark.gpu
+
+
+def check_against_oracle(ab, k, nrhs=1, seed=0, check_elementwise=True):
+    l_gpu, info = gpu_factor(ab, k)
+    assert info == 0
+    l_or, info_or = oracle.factor(ab, k)
+    assert info_or == 0
+    eta = oracle.llt_residual(l_gpu, ab, k)
+    assert eta <= ETA_TOL, eta
+    # padding rows and the bottom-right triangle are never written
+    n = ab.shape[1]
+    kk = min(k, n - 1) if n else 0
+    assert np.array_equal(l_gpu[kk + 1:], ab[kk + 1:])
+    for j in range(max(n - kk, 0), n):
+        assert np.array_equal(l_gpu[n - j: kk + 1, j], ab[n - j: kk + 1, j])
+    if check_elementwise:
+        assert rel_fro(l_gpu[: kk + 1], l_or[: kk + 1]) <= 1e-13 * (kk + 1)
+    b = synth.rhs(n, nrhs, seed)
+    x_gpu = gpu_solve(l_gpu, k, b)
+    assert oracle.solve_residual(ab, k, x_gpu, b) <= ETA_TOL
+    x_or = oracle.solve(l_or, k, b)
+    return l_gpu, x_gpu, l_or, x_or
+
+
+def test_c0_diag_dominant_n2000_k50():
+    """The small configuration: n = 2000, k = 50, diagonally dominant."""
+    ab = synth.band_diagdom(2000, 50, 0)
+    _, x_gpu, _, x_or = check_against_oracle(ab, 50, nrhs=1, seed=0)
+    assert np.max(np.abs(x_gpu - x_or)) <= 1e-12 * np.max(np.abs(x_or)) * 10
+
+
+@pytest.mark.parametrize("n,k", [
+    (1, 0), (2, 1), (31, 3), (32, 31), (33, 32), (64, 5), (100, 33), (257, 64), (300, 299),
+    (1000, 0), (1000, 1), (1000, 31), (1000, 32), (1000, 33), (777, 65), (1500, 96), (2049, 130),
+    (3001, 200), (500, 257),
+])
+def test_ragged_shapes(n, k):
+    """Several tiles with a ragged tail in n, in k, or both; k >= n-1 is dense."""
+    ab = synth.band_diagdom(n, k, 1000 * n + k)
+    check_against_oracle(ab, k, nrhs=2, seed=n + k)
+
+
+@pytest.mark.parametrize("ldab_extra", [1, 7])
+def test_ldab_padding_untouched(ldab_extra):
+    n, k = 700, 40
+    ab = synth.band_diagdom(n, k, 5, ldab=k + 1 + ldab_extra, fill=np.nan)
+    for j in range(n - k, n):
+        ab[n - j: k + 1, j] = np.nan                 # never referenced
+    l_gpu, info = gpu_factor(ab, k)
+    assert info == 0
+    assert np.all(np.isnan(l_gpu[k + 1:]))
+    ref = synth.band_diagdom(n, k, 5)
+    l_or, _ = oracle.factor(ref, k)
+    lg = l_gpu[: k + 1].copy()
+    for j in range(n - k, n):
+        assert np.all(np.isnan(lg[n - j:, j]))
+        lg[n - j:, j] = 0.0
+    assert rel_fro(lg, l_or) <= 1e-13 * (k + 1)
+
+
+@pytest.mark.parametrize("n,k,p2", [(3000, 50, 0), (2000, 100, 2), (1000, 250, 0), (500, 499, 1)])
+def test_integer_exact_bitwise(n, k, p2):
+    l0 = synth.int_factor(n, k, 17 + k, pow2_max=p2)
+    a = synth.band_ldlt(l0, k)
+    l_gpu, info = gpu_factor(a, k)
+    assert info == 0
+    assert np.array_equal(l_gpu, l0)
+    x0 = synth.int_vector(3 * n, 3).reshape(n, 3, order="F")
+    b = synth.band_symv(a, k, x0)
+    x = gpu_solve(l_gpu, k, b)
+    assert np.array_equal(x, x0)
+
+
+@pytest.mark.parametrize("m", [0, 1, 31, 32, 33, 64, 255, 599])
+@pytest.mark.parametrize("dval", [-1.0, 0.0])
+def test_nonspd_info_matches_oracle(m, dval):
+    n, k = 600, 40
+    l0 = synth.int_factor(n, k, 99)
+    dvec = np.ones(n)
+    dvec[m] = dval
+    a = synth.band_ldlt(l0, k, dvec)
+    _, info = gpu_factor(a, k)
+    assert info == m + 1 == oracle.factor(a, k)[1]
+
+
+def test_nan_info_matches_oracle():
+    n, k = 400, 45
+    base = synth.band_diagdom(n, k, 21)
+    for (i, j) in ((0, 0), (5, 5), (40, 9), (250, 240), (399, 360), (100, 55)):
+        ab = base.copy(order="F")
+        ab[i - j, j] = np.nan
+        _, info = gpu_factor(ab, k)
+        assert info == i + 1 == oracle.factor(ab, k)[1], (i, j)
+
+
+def test_run_to_run_bitwise():
+    ab, _ = synth.band_ipm(5000, 120, 7)
+    l1, _ = gpu_factor(ab, 120)
+    l2, _ = gpu_factor(ab, 120)
+    assert np.array_equal(l1, l2)
+    b = synth.rhs(5000, 2, 1)
+    assert np.array_equal(gpu_solve(l1, 120, b), gpu_solve(l1, 120, b))
+
+
+@pytest.mark.parametrize("k", [50, 100, 250])
+def test_ipm_recipe_forward_error(k):
+    """Ill-conditioned interior-point-like matrices (shift 1e-8 ||A||)."""
+    n = 20000
+    ab, _ = synth.band_ipm(n, k, 1000 + k)
+    l_gpu, x_gpu, l_or, x_or = check_against_oracle(ab, k, nrhs=1, seed=k, check_elementwise=False)
+    kap = oracle.cond1_estimate(ab, l_or, k)
+    fwd = np.max(np.abs(x_gpu - x_or)) / np.max(np.abs(x_or))
+    assert fwd <= 1e-12 * kap, (fwd, kap)
