@@ -1,0 +1,224 @@
+"""Benchmark: FP64 band Cholesky factor + solve on one MI355X.
+
+One step = the whole hot path over the workload: for every bandwidth k of the
+sweep, restore A from a pristine device copy (device-to-device), factor it
+(bandchol_factor_async) and solve one right-hand side (bandchol_solve_async).
+Inputs are synthetic, generated on the host with the interior-point-like
+recipe (A = L0 L0^T + 1e-8 ||A||_inf I, L0 diagonal 10^U[-4,0], off-diagonals
+N(0,1)/sqrt(k)), n = 100000, and are resident in HBM before timing starts.
+
+value = sum_k [n(k^2+3k) + 4 n k nrhs] / (wall time of one step): factor and
+solve flops over the whole step, restores included.  The factor rate per k is
+reported separately from HIP events on the launch stream.
+
+Prints ONE JSON line.  N > 1 GPUs is refused: this build runs on one GPU.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (vector = matrix)
+PEAK_HBM_GBS = 8000.0
+DEFAULT_KS = (50, 100, 250, 500, 1000, 2000)
+
+
+def factor_flops(n, k):
+    """The paper's flop model for the factorization (Section 3.2): n(k^2 + 3k)."""
+    return n * (k * k + 3 * k)
+
+
+def solve_flops(n, k, nrhs):
+    return 4 * n * k * nrhs
+
+
+def source_hash():
+    h = hashlib.sha256()
+    src = os.path.join(ROOT, "paper_2305_04635_amd", "csrc", "bandchol.hip")
+    h.update(open(src, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(ks, n_sample, seed0):
+    """The oracle (plain FP64 CPU, one thread) on the first n_sample rows of each matrix."""
+    import oracle
+    import synth
+    tot_flops, tot_t = 0.0, 0.0
+    for k in ks:
+        ab, _ = synth.band_ipm(n_sample, k, seed0 + k)
+        t0 = time.perf_counter()
+        info = oracle.pbtrf(ab, k)
+        tot_t += time.perf_counter() - t0
+        assert info == 0, info
+        tot_flops += factor_flops(n_sample, k)
+    return {
+        "value": round(tot_flops / tot_t / 1e9, 4),
+        "unit": "GFLOP/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": "factor only, the first %d rows of each matrix of the sweep k=%s (same recipe), "
+                  "%.1f s of CPU time" % (n_sample, ",".join(map(str, ks)), tot_t),
+    }
+
+
+def traffic_from_profile(kernel_hash):
+    path = os.path.join(ROOT, "profiles", "factor_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except ValueError:
+        return None
+    if d.get("source_hash") != kernel_hash:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=100000)
+    ap.add_argument("--ks", type=str, default=",".join(map(str, DEFAULT_KS)))
+    ap.add_argument("--nrhs", type=int, default=1)
+    ap.add_argument("--seed", type=int, default=1000)
+    ap.add_argument("--cpu-rows", type=int, default=10000, help="rows per matrix for the oracle baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--check", action="store_true", help="sampled backward-error check after timing")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on exactly one GPU (the band factorization of one matrix is "
+              "a single dependency chain); --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2305_04635_amd as bc
+
+    ks = [int(x) for x in args.ks.split(",")]
+    n, nrhs = args.n, args.nrhs
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    bc.load()
+
+    # inputs, resident in HBM before timing
+    t_gen = time.perf_counter()
+    mats = []
+    for k in ks:
+        ab, _ = synth.band_ipm(n, k, args.seed + k)
+        b = synth.rhs(n, nrhs, args.seed + k)
+        pristine = torch.from_numpy(ab.ravel(order="F")).to(dev)
+        b0 = torch.from_numpy(b.ravel(order="F")).to(dev)
+        mats.append(dict(k=k, ab0=pristine, ab=torch.empty_like(pristine), b0=b0, b=torch.empty_like(b0),
+                         info=torch.zeros(1, dtype=torch.int64, device=dev), host_ab=ab if args.check else None))
+        del ab
+    t_gen = time.perf_counter() - t_gen
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+
+    def step(events):
+        for i, m in enumerate(mats):
+            m["ab"].copy_(m["ab0"])
+            m["b"].copy_(m["b0"])
+            e0, e1, e2 = events[i] if events else (None, None, None)
+            if e0 is not None:
+                e0.record(stream)
+            bc.factor_async(m["ab"], n, m["k"], m["info"])
+            if e1 is not None:
+                e1.record(stream)
+            bc.solve_async(m["ab"], n, m["k"], m["b"], nrhs=nrhs)
+            if e2 is not None:
+                e2.record(stream)
+
+    for _ in range(args.warmup):
+        step(None)
+    torch.cuda.synchronize()
+
+    evs = [[[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in mats] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(evs[s])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+
+    infos = [int(m["info"].item()) for m in mats]
+    if any(i != 0 for i in infos):
+        print("bench.py: factorization failed, info per k = %s" % infos, file=sys.stderr)
+        sys.exit(1)
+
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    per_k = []
+    tot_factor_ms, tot_factor_flops = 0.0, 0.0
+    for i, m in enumerate(mats):
+        f_ms = float(np.median([evs[s][i][0].elapsed_time(evs[s][i][1]) for s in range(args.steps)]))
+        s_ms = float(np.median([evs[s][i][1].elapsed_time(evs[s][i][2]) for s in range(args.steps)]))
+        f_mean = float(np.mean([evs[s][i][0].elapsed_time(evs[s][i][1]) for s in range(args.steps)]))
+        ff = factor_flops(n, m["k"])
+        tot_factor_ms += f_mean
+        tot_factor_flops += ff
+        per_k.append({"k": m["k"], "factor_ms": round(f_ms, 4), "solve_ms": round(s_ms, 4),
+                      "factor_gflops": round(ff / (f_ms * 1e-3) / 1e9, 2),
+                      "factor_frac_fp64_peak": round(ff / (f_ms * 1e-3) / (PEAK_FP64_TFLOPS * 1e12), 5),
+                      "factor_frac_hbm": round(16.0 * n * (m["k"] + 1) / (f_ms * 1e-3) / (PEAK_HBM_GBS * 1e9), 5)})
+
+    step_flops = sum(factor_flops(n, k) + solve_flops(n, k, nrhs) for k in ks)
+    value = step_flops / (ms_step * 1e-3) / 1e9
+
+    # dominant kernel: the factor kernel; achieved = average algorithmic flops per launch / average launch time
+    nlaunch = len(mats)
+    achieved = (tot_factor_flops / nlaunch) / (tot_factor_ms / nlaunch * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP64_TFLOPS, 5), "traffic": traffic_from_profile(source_hash()),
+                "kernel": "factor_kernel", "avg_launch_ms": round(tot_factor_ms / nlaunch, 4),
+                "avg_flops_per_launch": tot_factor_flops / nlaunch}
+
+    check = None
+    if args.check:
+        import oracle
+        worst = 0.0
+        for m in mats:
+            l = m["ab"].cpu().numpy().reshape(m["host_ab"].shape, order="F")
+            rows = [(r, r + 64) for r in (0, n // 2, n - 64)]
+            worst = max(worst, oracle.llt_residual(l, m["host_ab"], m["k"], rows=rows))
+        check = {"sampled_backward_error_max": worst}
+
+    line = {
+        "metric": "band Cholesky GFLOP/s n=1e5,k=50-2000 (FP64 factor+solve, one sweep per step)",
+        "value": round(value, 3),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "band Cholesky factor + solve, n=%d, k in {%s}, nrhs=%d, interior-point-like "
+                               "SPD band (A = L0 L0^T + 1e-8||A|| I), LAPACK lower band ldab=k+1"
+                               % (n, ",".join(map(str, ks)), nrhs),
+                   "n": n, "ks": ks, "nrhs": nrhs, "tile": bc.tile(), "per_k": per_k,
+                   "input_generation_s": round(t_gen, 2)},
+        "roofline": roofline,
+    }
+    if check is not None:
+        line["check"] = check
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(ks, args.cpu_rows, args.seed)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()
