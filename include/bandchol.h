@@ -94,6 +94,15 @@ void bandchol_finalize(void);
 /* Tile width the factor uses (the rank of each trailing update). */
 int64_t bandchol_tile(void);
 
+/*
+ * Tuning: single matrices whose band spans at most `kmax` sub-diagonal tiles
+ * (k <= kmax * bandchol_tile()) are factored by one workgroup walking the band;
+ * wider bands use the multi-workgroup tile schedule.  kmax is clamped to
+ * [0, 15].  Returns the previous limit; a negative kmax only queries it.
+ * Process-wide; not synchronised with calls running in other threads.
+ */
+int64_t bandchol_set_walk_limit(int64_t kmax);
+
 #ifdef __cplusplus
 }
 #endif

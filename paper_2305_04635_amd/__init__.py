@@ -30,6 +30,7 @@ SIGNATURES = {
     "bandchol_last_error": (ctypes.c_char_p, []),
     "bandchol_finalize": (None, []),
     "bandchol_tile": (_I64, []),
+    "bandchol_set_walk_limit": (_I64, [_I64]),
 }
 
 EHIP = -1000
@@ -75,6 +76,11 @@ def _raise(rc, what):
 
 def tile():
     return int(load().bandchol_tile())
+
+
+def set_walk_limit(kmax):
+    """Largest sub-diagonal tile count factored by the single-workgroup walk; returns the previous value."""
+    return int(load().bandchol_set_walk_limit(int(kmax)))
 
 
 def factor(ab, n, k, ldab=None):

@@ -30,51 +30,18 @@
 
 #include "bandchol.h"
 
+#include "common.h"
+
+size_t bandchol_solve_workspace(int64_t n);
+hipError_t bandchol_solve_launch(int64_t n, int64_t k, int64_t nrhs, const double* ab, int64_t ldab, double* b,
+                                 int64_t ldb, void* ws, int num_cus, hipStream_t st);
+
 namespace {
 
-constexpr int T = 32;        // tile width
+using namespace bandchol;
+
 constexpr int NT = 256;      // threads per workgroup (4 waves)
-constexpr int LP = T + 1;    // LDS pitch of a staged tile (column-major)
 constexpr long long SPIN_LIMIT = 1LL << 25;
-
-typedef double d4 __attribute__((ext_vector_type(4)));
-
-// ----------------------------------------------------------------- device helpers
-
-__device__ __forceinline__ double readlane_d(double v, int lane) {
-  int2 p = __builtin_bit_cast(int2, v);
-  p.x = __builtin_amdgcn_readlane(p.x, lane);
-  p.y = __builtin_amdgcn_readlane(p.y, lane);
-  return __builtin_bit_cast(double, p);
-}
-
-// One 16x16x4 FP64 MFMA step of D += X Y^T restricted to a 16x16 block, where
-// xf and yf are the fragments "lane l holds M[16*blk + l%16][k0 + l/16]" of X
-// and Y.  The accumulator then holds, in lane l and register r, the block
-// element (row l%16, column 4r + l/16): consecutive lanes are consecutive rows,
-// which in the column-major band layout are consecutive addresses.
-#ifndef BANDCHOL_MFMA_SWAP
-#define BANDCHOL_MFMA_SWAP 1
-#endif
-__device__ __forceinline__ d4 mfma_xyt(double xf, double yf, d4 acc) {
-#if BANDCHOL_MFMA_SWAP
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(yf, xf, acc, 0, 0, 0);
-#else
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(xf, yf, acc, 0, 0, 0);
-#endif
-}
-
-struct Band {
-  double* ab;
-  int64_t n, k, ldab;
-  __device__ __forceinline__ bool in_band(int64_t i, int64_t j) const {
-    int64_t d = i - j;
-    return i < n && d >= 0 && d <= k;
-  }
-  __device__ __forceinline__ double ld(int64_t i, int64_t j) const {
-    return in_band(i, j) ? ab[(i - j) + j * ldab] : 0.0;
-  }
-};
 
 struct Work {
   int* flags;          // NB * (K+1) tile-ready flags, tile (R, R-d) at R*(K+1)+d
@@ -90,7 +57,7 @@ __device__ __forceinline__ int ld_flag(const int* f) {
 
 // Thread 0 waits for up to two flags; the whole workgroup learns whether to go
 // on.  Every wave then performs its own acquire before reading tile data.
-__device__ bool wg_wait(const int* f1, const int* f2, const Work& w, int* s_ok) {
+__device__ bool wg_wait(const int* f1, const int* f2, const Work& w, lds_i* s_ok) {
   if (threadIdx.x == 0) {
     int ok = 1;
     long long spins = 0;
@@ -162,36 +129,15 @@ __device__ __forceinline__ d4 tile_load(const Band& a, int R, int C, int bi, int
   return acc;
 }
 
-__device__ __forceinline__ void acc_to_lds(double* lds, int bi, int bj, d4 acc) {
+__device__ __forceinline__ void acc_to_lds(lds_d* lds, int bi, int bj, d4 acc) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int r = 0; r < 4; ++r) lds[(16 * bj + 4 * r + (lane >> 4)) * LP + 16 * bi + (lane & 15)] = acc[r];
 }
 
-// Dense Cholesky of the staged diagonal tile (lanes 0..T-1 = its rows) with
-// the identity rows in lanes T..2T-1 swept along: afterwards lane i < T holds
-// row i of L and lane T+b holds row b of L^{-T}.  Right-looking, one column
-// per step; the column of L is broadcast with readlane.  Returns the first
-// failing local column or -1.
-__device__ int sweep_potrf(double (&row)[T]) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int j = 0; j < T; ++j) {
-    const double d = readlane_d(row[j], j);
-    if (!(d > 0.0)) return j;
-    const double r = sqrt(d);
-    const double y = 1.0 / r;
-    const double lij = (lane == j) ? r : row[j] * y;
-    row[j] = lij;
-#pragma unroll
-    for (int l = j + 1; l < T; ++l) row[l] = fma(-lij, readlane_d(lij, l), row[l]);
-  }
-  return -1;
-}
-
 // Each task body is compiled on its own (noinline) so that the two term loops
 // are never merged into one.
-__device__ __attribute__((noinline)) void diag_task(const FactorParams& P, int C, double* lds, int* s_ok) {
+__device__ __attribute__((noinline)) void diag_task(const FactorParams& P, int C, lds_d* lds, lds_d* wbuf, lds_i* s_ok) {
   const Band& a = P.a;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int bi = wave & 1, bj = wave >> 1;
@@ -211,7 +157,7 @@ __device__ __attribute__((noinline)) void diag_task(const FactorParams& P, int C
 #pragma unroll
     for (int c = 0; c < T; ++c)
       row[c] = lane < T ? lds[c * LP + lane] : ((lane - T) == c ? 1.0 : 0.0);
-    const int fail = sweep_potrf(row);
+    const int fail = sweep_ldlt(row, wbuf);
     if (fail >= 0) {
       const long long col = (long long)C * T + fail;
       if (lane == 0 && col < a.n) {
@@ -236,7 +182,7 @@ __device__ __attribute__((noinline)) void diag_task(const FactorParams& P, int C
   wg_publish(&P.w.flags[C * (P.K + 1)]);
 }
 
-__device__ __attribute__((noinline)) void off_task(const FactorParams& P, int R, int C, double* lds, int* s_ok) {
+__device__ __attribute__((noinline)) void off_task(const FactorParams& P, int R, int C, lds_d* lds, lds_i* s_ok) {
   const Band& a = P.a;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int bi = wave & 1, bj = wave >> 1;
@@ -274,6 +220,7 @@ __device__ __attribute__((noinline)) void off_task(const FactorParams& P, int R,
 
 __global__ void __launch_bounds__(NT) factor_kernel(FactorParams P) {
   __shared__ double lds[T * LP];
+  __shared__ double wbuf[64];
   __shared__ int s_task, s_ok, s_abort;
   for (;;) {
     if (threadIdx.x == 0) {
@@ -286,8 +233,8 @@ __global__ void __launch_bounds__(NT) factor_kernel(FactorParams P) {
     const int C = (int)(t / (unsigned)(P.K + 1));
     const int d = (int)(t % (unsigned)(P.K + 1));
     if (C + d < P.NB) {
-      if (d == 0) diag_task(P, C, lds, &s_ok);
-      else off_task(P, C + d, C, lds, &s_ok);
+      if (d == 0) diag_task(P, C, (lds_d*)lds, (lds_d*)wbuf, (lds_i*)&s_ok);
+      else off_task(P, C + d, C, (lds_d*)lds, (lds_i*)&s_ok);
     }
     __syncthreads();
   }
@@ -310,133 +257,204 @@ __global__ void factor_finish_kernel(const int* abort_flag, const unsigned long 
   *d_info = (ab == 2) ? (int64_t)BANDCHOL_EHANG : (ff == 0x7fffffffffffffffULL ? 0 : (int64_t)ff);
 }
 
-// ----------------------------------------------------------------- solves
+// ----------------------------------------------------------------- single-workgroup walk
+//
+// One workgroup factors one matrix, right-looking and in place, with no
+// communication outside the workgroup.  Per tile column C:
+//   phase A  wave 0: sweep of the staged diagonal tile -> L(C,C), L(C,C)^{-T};
+//            waves 1-3: the work of column C-1 that the next diagonal tile does
+//            not wait for: trsm of tiles (C-1+d, C-1), d >= 2, then the updates
+//            tile(C-1+dr, C-1+dc) -= L(C-1+dr, C-1) L(C-1+dc, C-1)^T, all pairs but (1,1);
+//   phase B  all waves: trsm of tile (C+1, C) (the critical one);
+//   phase C  waves 1-3: diag = tile(C+1, C+1) - L(C+1, C) L(C+1, C)^T, staged for the next sweep.
+// The current tile column's L tiles stay in LDS (pnl) for the updates.
 
-// Per diagonal tile, L(C,C)^{-T} (row-major) from the factor: lanes 0..T-1
-// hold the rows of L(C,C), lanes T..2T-1 the identity rows, which are solved
-// against L(C,C) column by column.
-__global__ void __launch_bounds__(64) solve_tri_inv_kernel(Band a, int NB, double* dinvt) {
-  const int C = blockIdx.x, lane = threadIdx.x;
+constexpr int WALK_KMAX = 15;
+
+// Trsm of a tile in place: every output block needs the input row-block over all
+// columns, so all input fragments are read before any output is written.
+// Fragments of row-block bi of tile (R, C): x[q] = A(R*T + 16 bi + l%16, C*T + 4q + l/16).
+__device__ __forceinline__ void rowblk_load(const Band& a, int64_t R, int64_t C, int bi, double (&x)[T / 4]) {
+  const int lane = lane_id();
+  const int64_t i = R * T + 16 * bi + (lane & 15);
+#pragma unroll
+  for (int q = 0; q < T / 4; ++q) x[q] = a.ld(i, C * T + 4 * q + (lane >> 4));
+}
+
+// out block (bi, bj) = X_rowblk * L^{-T}(:, 16bj..16bj+15); L^{-T} row-major in LDS, upper triangular.
+__device__ __forceinline__ d4 blk_trsm_frag(const double (&x)[T / 4], const lds_d* linvt, int bj) {
+  const int lane = lane_id();
+  const int qmax = 4 * bj + 4;
+  d4 out = {0, 0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < T / 4; ++q)
+    if (q < qmax) out = mfma_xyt(x[q], linvt[(4 * q + (lane >> 4)) * T + 16 * bj + (lane & 15)], out);
+  return out;
+}
+
+// One wave: tile (R, C) <- tile (R, C) * L(C,C)^{-T}, written to global and to an LDS copy.
+__device__ __forceinline__ void tile_trsm_wave(const Band& a, int64_t R, int64_t C, const lds_d* linvt, lds_d* lds_out) {
+  double x0[T / 4], x1[T / 4];
+  rowblk_load(a, R, C, 0, x0);
+  rowblk_load(a, R, C, 1, x1);
+  const d4 o00 = blk_trsm_frag(x0, linvt, 0), o01 = blk_trsm_frag(x0, linvt, 1);
+  const d4 o10 = blk_trsm_frag(x1, linvt, 0), o11 = blk_trsm_frag(x1, linvt, 1);
+  blk_to_lds(lds_out, 0, 0, o00); blk_to_lds(lds_out, 0, 1, o01);
+  blk_to_lds(lds_out, 1, 0, o10); blk_to_lds(lds_out, 1, 1, o11);
+  blk_store(a, R, C, 0, 0, o00); blk_store(a, R, C, 0, 1, o01);
+  blk_store(a, R, C, 1, 0, o10); blk_store(a, R, C, 1, 1, o11);
+}
+
+struct WalkLds {
+  lds_d* diag;    // T*LP
+  lds_d* linvt;   // 2 * T*T
+  lds_d* pnl;     // K * T*LP
+  lds_d* wbuf;    // 64
+};
+
+__device__ __forceinline__ WalkLds walk_lds(lds_d* base, int K) {
+  WalkLds L;
+  L.diag = base;
+  L.linvt = L.diag + T * LP;
+  L.pnl = L.linvt + 2 * T * T;
+  L.wbuf = L.pnl + (size_t)K * T * LP;
+  return L;
+}
+
+size_t walk_lds_bytes(int K) { return sizeof(double) * ((size_t)T * LP + 2 * T * T + (size_t)K * T * LP + 64); }
+
+// wave 0: factor the staged diagonal tile, store L(C,C), keep L(C,C)^{-T} in LDS
+__device__ __attribute__((noinline)) void walk_sweep(const Band& a, int64_t C, const WalkLds& L, lds_d* lt, lds_i* s_fail) {
+  const int lane = lane_id();
   double row[T];
-  const int64_t i = (int64_t)C * T + lane;
+#pragma unroll
+  for (int c = 0; c < T; ++c) row[c] = lane < T ? L.diag[c * LP + lane] : ((lane - T) == c ? 1.0 : 0.0);
+  const int fail = sweep_ldlt(row, L.wbuf);
+  if (fail >= 0) {
+    if (lane == 0) *s_fail = fail;
+    return;
+  }
+  const int64_t i = C * T + lane;
 #pragma unroll
   for (int c = 0; c < T; ++c) {
-    const int64_t j = (int64_t)C * T + c;
-    if (lane < T) row[c] = (i >= a.n && i == j) ? 1.0 : a.ld(i, j);
-    else row[c] = ((lane - T) == c) ? 1.0 : 0.0;
-  }
-  const bool rhs = lane >= T;
-#pragma unroll
-  for (int j = 0; j < T; ++j) {
-    const double y = 1.0 / readlane_d(row[j], j);
-    const double x = rhs ? row[j] * y : row[j];   // lanes < T keep L
-    row[j] = x;
-#pragma unroll
-    for (int l = j + 1; l < T; ++l) {
-      const double llj = readlane_d(x, l);          // L(l, j), from lane l < T
-      row[l] = rhs ? fma(-x, llj, row[l]) : row[l];
+    if (lane < T) {
+      if (c <= lane && i < a.n) *a.at(i, C * T + c) = row[c];
+    } else {
+      lt[(lane - T) * T + c] = row[c];
     }
-  }
-  if (lane >= T) {
-#pragma unroll
-    for (int c = 0; c < T; ++c) dinvt[(int64_t)C * T * T + (lane - T) * T + c] = row[c];
   }
 }
 
-// Forward solve L y = b for one right-hand side per workgroup.  The rows
-// [C*T, C*T+T+k) that still receive updates live in an LDS ring of W slots.
-__global__ void __launch_bounds__(NT) solve_fwd_kernel(Band a, int NB, const double* dinvt, double* b, int64_t ldb,
-                                                      int W) {
-  extern __shared__ double ring[];
-  __shared__ double ys[T];
-  double* bc = b + (int64_t)blockIdx.x * ldb;
-  const int tid = threadIdx.x;
-  const int64_t n = a.n, k = a.k;
-  const int64_t first = (T + k < n) ? T + k : n;
-  for (int64_t r = tid; r < first; r += NT) ring[r & (W - 1)] = bc[r];
+// waves 1-3: the rest of tile column Cp (trsm of d >= 2, then all updates but the critical one)
+__device__ __attribute__((noinline)) void walk_column_rest(const Band& a, int K, int64_t NB, int64_t Cp,
+                                                           const WalkLds& L, const lds_d* lt_prev, lds_i* s_sync,
+                                                           int sync_target) {
+  const int wave = wave_id(), lane = lane_id();
+  for (int d = 2; d <= K && Cp + d < NB; ++d)
+    if ((d - 2) % 3 == wave - 1) tile_trsm_wave(a, Cp + d, Cp, lt_prev, L.pnl + (size_t)(d - 1) * T * LP);
+  int idx = 0;
+  // waves 1-3 meet before using each other's panel tiles
+  __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): this wave's LDS writes are done
+  if (lane == 0) __hip_atomic_fetch_add(s_sync, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+  while (__hip_atomic_load(s_sync, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < sync_target)
+    __builtin_amdgcn_s_sleep(1);
+  for (int dr = 1; dr <= K && Cp + dr < NB; ++dr) {
+    for (int dc = 1; dc <= dr; ++dc) {
+      if (dr == 1 && dc == 1) continue;
+      for (int blk = 0; blk < 4; ++blk) {
+        const int bi = blk & 1, bj = blk >> 1;
+        if (dr == dc && bj > bi) continue;
+        if (idx++ % 3 != wave - 1) continue;
+        d4 acc = blk_load(a, Cp + dr, Cp + dc, bi, bj);
+        acc = blk_gemm_lds(L.pnl + (size_t)(dr - 1) * T * LP, L.pnl + (size_t)(dc - 1) * T * LP, bi, bj, acc);
+        blk_store(a, Cp + dr, Cp + dc, bi, bj, acc);
+      }
+    }
+  }
+}
+
+// Returns info (0 or the 1-based failing column).
+__device__ int64_t walk_factor(const Band a, const int K, const WalkLds L, lds_i* s_fail, lds_i* s_sync) {
+  const int wave = wave_id();
+  const int64_t NB = (a.n + T - 1) / T;
+  if (threadIdx.x == 0) { *s_fail = -1; *s_sync = 0; }
+  // stage tile (0, 0)
+  if (wave >= 1) {
+    const int bi = (wave >= 2), bj = (wave == 3);
+    blk_to_lds(L.diag, bi, bj, blk_load(a, 0, 0, bi, bj));
+  } else {
+    blk_to_lds(L.diag, 0, 1, d4{0, 0, 0, 0});
+  }
   __syncthreads();
-  for (int C = 0; C < NB; ++C) {
-    const int64_t c0 = (int64_t)C * T;
-    const double* lt = dinvt + (int64_t)C * T * T;
-    {  // y_C = L(C,C)^{-1} b_C: y[i] = sum_c Linvt[c][i] b[c]; 8 lanes per row
-      const int i = tid >> 3, p = tid & 7;
-      double s = 0.0;
-#pragma unroll
-      for (int q = 0; q < T / 8; ++q) {
-        const int c = p * (T / 8) + q;
-        const double bv = (c0 + c < n) ? ring[(c0 + c) & (W - 1)] : 0.0;
-        s = fma(lt[c * T + i], bv, s);
-      }
-      s += __shfl_xor(s, 1);
-      s += __shfl_xor(s, 2);
-      s += __shfl_xor(s, 4);
-      if (p == 0) {
-        ys[i] = s;
-        if (c0 + i < n) bc[c0 + i] = s;
-      }
-    }
+  int sync_target = 0;
+  for (int64_t C = 0; C < NB; ++C) {
+    lds_d* lt = L.linvt + (C & 1) * T * T;
+    const lds_d* lt_prev = L.linvt + ((C + 1) & 1) * T * T;
+    // ---------------- phase A
+    if (wave == 0) walk_sweep(a, C, L, lt, s_fail);
+    else if (C >= 1) walk_column_rest(a, K, NB, C - 1, L, lt_prev, s_sync, sync_target += 3);
+    wait_vmem();
     __syncthreads();
-    // rows [c0+T, c0+T+k) -= L(r, c0+c) y_c
-    const int64_t rlo = c0 + T, rhi = (c0 + T + k < n) ? c0 + T + k : n;
-    for (int64_t r = rlo + tid; r < rhi; r += NT) {
-      double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-      for (int c = 0; c < T; c += 2) {
-        s0 = fma(a.ld(r, c0 + c), ys[c], s0);
-        s1 = fma(a.ld(r, c0 + c + 1), ys[c + 1], s1);
-      }
-      ring[r & (W - 1)] -= s0 + s1;
+    if (*s_fail >= 0) return C * T + *s_fail + 1;
+    if (C + 1 >= NB) break;
+    // ---------------- phase B: trsm of tile (C+1, C)
+    if (K >= 1) {
+      const int bi = wave & 1, bj = wave >> 1;
+      double x[T / 4];
+      rowblk_load(a, C + 1, C, bi, x);
+      wait_vmem();
+      __syncthreads();   // every wave holds its input before any output is written
+      const d4 out = blk_trsm_frag(x, lt, bj);
+      blk_to_lds(L.pnl, bi, bj, out);
+      blk_store(a, C + 1, C, bi, bj, out);
     }
-    // rows entering the window for the next tile
-    const int64_t elo = c0 + T + k, ehi = (c0 + 2 * T + k < n) ? c0 + 2 * T + k : n;
-    for (int64_t r = elo + tid; r < ehi; r += NT) ring[r & (W - 1)] = bc[r];
+    wait_vmem();
+    __syncthreads();
+    // ---------------- phase C: stage tile (C+1, C+1) minus the critical update
+    if (wave >= 1) {
+      const int bi = (wave >= 2), bj = (wave == 3);
+      d4 acc = blk_load(a, C + 1, C + 1, bi, bj);
+      if (K >= 1) acc = blk_gemm_lds(L.pnl, L.pnl, bi, bj, acc);
+      blk_to_lds(L.diag, bi, bj, acc);
+    } else {
+      blk_to_lds(L.diag, 0, 1, d4{0, 0, 0, 0});
+    }
     __syncthreads();
   }
+  return 0;
 }
 
-// Back solve L^T x = y, tiles in descending order.  x_C = L(C,C)^{-T} (y_C - z)
-// with z_c = sum_{r >= (C+1)T} L(r, c0+c) x_r; the known x of the next k rows
-// live in the LDS ring.
-__global__ void __launch_bounds__(NT) solve_bwd_kernel(Band a, int NB, const double* dinvt, double* b, int64_t ldb,
-                                                      int W) {
-  extern __shared__ double ring[];
-  __shared__ double zs[T];
-  double* bc = b + (int64_t)blockIdx.x * ldb;
-  const int tid = threadIdx.x;
-  const int64_t n = a.n, k = a.k;
-  for (int C = NB - 1; C >= 0; --C) {
-    const int64_t c0 = (int64_t)C * T;
-    const double* lt = dinvt + (int64_t)C * T * T;
-    {  // z_c = y_c - sum_r L(r, c0+c) x_r over r in [c0+T, c0+c+k]
-      const int c = tid >> 3, p = tid & 7;
-      const int64_t j = c0 + c;
-      const int64_t rlo = c0 + T;
-      int64_t rhi = j + k + 1;
-      if (rhi > n) rhi = n;
-      double s = 0.0;
-      for (int64_t r = rlo + p; r < rhi; r += 8) s = fma(a.ld(r, j), ring[r & (W - 1)], s);
-      s += __shfl_xor(s, 1);
-      s += __shfl_xor(s, 2);
-      s += __shfl_xor(s, 4);
-      if (p == 0) zs[c] = (j < n) ? bc[j] - s : 0.0;
-    }
+struct WalkSys {
+  double* ab;
+  int64_t n, k, ldab;
+};
+
+__global__ void __launch_bounds__(NT) walk_single_kernel(WalkSys w, int K, int64_t* info) {
+  extern __shared__ double lds_dyn[];
+  __shared__ int s_fail, s_sync;
+  const Band a{(glb_d*)w.ab, w.n, w.k, w.ldab};
+  const int64_t res = walk_factor(a, K, walk_lds((lds_d*)lds_dyn, K), (lds_i*)&s_fail, (lds_i*)&s_sync);
+  if (threadIdx.x == 0) *info = res;
+}
+
+// Persistent: each workgroup takes systems from the queue in the given order.
+__global__ void __launch_bounds__(NT) walk_kernel(const WalkSys* sys, const int* order, int nsys, int Kmax,
+                                                  unsigned* queue, int64_t* info) {
+  extern __shared__ double lds_dyn[];
+  __shared__ int s_idx, s_fail, s_sync;
+  for (;;) {
+    if (threadIdx.x == 0) s_idx = (int)atomicAdd(queue, 1u);
     __syncthreads();
-    {  // x_C[i] = sum_c Linvt[i][c] z[c]
-      const int i = tid >> 3, p = tid & 7;
-      double s = 0.0;
-#pragma unroll
-      for (int q = 0; q < T / 8; ++q) {
-        const int c = p * (T / 8) + q;
-        s = fma(lt[i * T + c], zs[c], s);
-      }
-      s += __shfl_xor(s, 1);
-      s += __shfl_xor(s, 2);
-      s += __shfl_xor(s, 4);
-      if (p == 0 && c0 + i < n) {
-        ring[(c0 + i) & (W - 1)] = s;
-        bc[c0 + i] = s;
-      }
-    }
+    const int t = s_idx;
+    if (t >= nsys) break;
+    const int id = order ? order[t] : t;
+    const WalkSys w = sys[id];
+    const int64_t kk = w.k < w.n - 1 ? w.k : (w.n > 0 ? w.n - 1 : 0);
+    int K = (int)((kk + T - 1) / T);
+    const Band a{(glb_d*)w.ab, w.n, kk, w.ldab};
+    int64_t res = 0;
+    if (w.n > 0) res = walk_factor(a, K, walk_lds((lds_d*)lds_dyn, Kmax), (lds_i*)&s_fail, (lds_i*)&s_sync);
+    if (threadIdx.x == 0) info[id] = res;
     __syncthreads();
   }
 }
@@ -527,6 +545,26 @@ int num_cus() {
   return g_num_cus;
 }
 
+// Largest sub-diagonal tile count handled by the single-workgroup walk.
+int g_walk_kmax = -1;
+int walk_kmax() {
+  if (g_walk_kmax < 0) {
+    g_walk_kmax = 2;
+    if (const char* e = getenv("BANDCHOL_WALK_KMAX")) g_walk_kmax = (int)strtol(e, nullptr, 10);
+    if (g_walk_kmax > WALK_KMAX) g_walk_kmax = WALK_KMAX;
+  }
+  return g_walk_kmax;
+}
+
+hipError_t walk_attr(size_t lds) {
+  static size_t done = 0;
+  if (lds <= done) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute((const void*)walk_single_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)walk_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e == hipSuccess) done = lds;
+  return e;
+}
+
 int64_t factor_async_impl(int64_t n, int64_t k, double* ab, int64_t ldab, int64_t* d_info, hipStream_t st) {
   if (n < 0) return -1;
   if (k < 0) return -2;
@@ -539,6 +577,16 @@ int64_t factor_async_impl(int64_t n, int64_t k, double* ab, int64_t ldab, int64_
   }
   hipError_t e;
   const FactorLayout L = factor_layout(n, k);
+  if (n > 0 && L.K <= walk_kmax()) {
+    const int64_t kk = k < n - 1 ? k : n - 1;
+    const size_t lds = walk_lds_bytes(L.K);
+    e = walk_attr(lds);
+    if (e != hipSuccess) { set_err("walk attributes", e); return BANDCHOL_EHIP; }
+    walk_single_kernel<<<1, NT, lds, st>>>(WalkSys{ab, n, kk, ldab}, L.K, d_info);
+    e = hipGetLastError();
+    if (e != hipSuccess) { set_err("factor launch", e); return BANDCHOL_EHIP; }
+    return 0;
+  }
   char* ws = (char*)workspace(L.total, &e);
   if (!ws) { set_err("workspace", e); return BANDCHOL_EHIP; }
   unsigned* queue = (unsigned*)(ws + 0);
@@ -550,7 +598,7 @@ int64_t factor_async_impl(int64_t n, int64_t k, double* ab, int64_t ldab, int64_
       flags, nflags, queue, abort_flag, first_fail);
   if (n > 0) {
     FactorParams P;
-    P.a = Band{ab, n, k, ldab};
+    P.a = Band{(glb_d*)ab, n, k, ldab};
     P.NB = L.NB;
     P.K = L.K;
     P.ntasks = (unsigned)((int64_t)L.NB * (L.K + 1));
@@ -580,26 +628,11 @@ int64_t solve_async_impl(int64_t n, int64_t k, int64_t nrhs, const double* ab, i
   if (b == nullptr && n > 0 && nrhs > 0) return -6;
   if (ldb < (n > 1 ? n : 1)) return -7;
   if (n == 0 || nrhs == 0) return 0;
-  const int NB = (int)((n + T - 1) / T);
-  int64_t kk = k < n - 1 ? k : n - 1;
-  int64_t W = 1;
-  while (W < kk + 2 * T) W <<= 1;
-  if (W > 8192) {
-    snprintf(g_err, sizeof g_err, "bandwidth too large for the solve window (k <= %d)", 8192 - 2 * T);
-    return -2;
-  }
+  const int64_t kk = k < n - 1 ? k : n - 1;
   hipError_t e;
-  const size_t need = align_up(sizeof(double) * (size_t)NB * T * T);
-  // the solve uses the top of the same per-device workspace after the factor's part
-  const FactorLayout L = factor_layout(n, k);
-  char* ws = (char*)workspace(L.total + need, &e);
+  void* ws = workspace(bandchol_solve_workspace(n), &e);
   if (!ws) { set_err("workspace", e); return BANDCHOL_EHIP; }
-  double* dinvt = (double*)(ws + L.total);
-  Band a{const_cast<double*>(ab), n, kk, ldab};
-  solve_tri_inv_kernel<<<NB, 64, 0, st>>>(a, NB, dinvt);
-  solve_fwd_kernel<<<(unsigned)nrhs, NT, W * sizeof(double), st>>>(a, NB, dinvt, b, ldb, (int)W);
-  solve_bwd_kernel<<<(unsigned)nrhs, NT, W * sizeof(double), st>>>(a, NB, dinvt, b, ldb, (int)W);
-  e = hipGetLastError();
+  e = bandchol_solve_launch(n, kk, nrhs, ab, ldab, b, ldb, ws, num_cus(), st);
   if (e != hipSuccess) { set_err("solve launch", e); return BANDCHOL_EHIP; }
   return 0;
 }
@@ -675,5 +708,12 @@ void bandchol_finalize(void) {
 }
 
 int64_t bandchol_tile(void) { return T; }
+
+int64_t bandchol_set_walk_limit(int64_t kmax) {
+  const int64_t prev = walk_kmax();
+  if (kmax < 0) return prev;
+  g_walk_kmax = (int)(kmax > WALK_KMAX ? WALK_KMAX : kmax);
+  return prev;
+}
 
 }  // extern "C"

@@ -127,3 +127,38 @@ def test_ipm_recipe_forward_error(k):
     kap = oracle.cond1_estimate(ab, l_or, k)
     fwd = np.max(np.abs(x_gpu - x_or)) / np.max(np.abs(x_or))
     assert fwd <= 1e-12 * kap, (fwd, kap)
+
+
+@pytest.fixture(params=["walk", "tiles"])
+def schedule(request):
+    import paper_2305_04635_amd as bc
+    prev = bc.set_walk_limit(15 if request.param == "walk" else 0)
+    yield request.param
+    bc.set_walk_limit(prev)
+
+
+@pytest.mark.parametrize("n,k", [(128, 70), (300, 299), (1000, 130), (777, 200), (2049, 33), (96, 95), (1, 0), (33, 1)])
+def test_both_schedules(schedule, n, k):
+    """The single-workgroup walk and the multi-workgroup tile schedule, each
+    forced on bands of several tile widths (the walk's in-place trsm of
+    K >= 3 tiles once raced: one wave read columns another wave had already
+    overwritten)."""
+    ab = synth.band_diagdom(n, k, 31 * n + k)
+    check_against_oracle(ab, k, nrhs=1, seed=k)
+    l0 = synth.int_factor(n, k, 5 + k, pow2_max=1)
+    a = synth.band_ldlt(l0, k)
+    l_gpu, info = gpu_factor(a, k)
+    assert info == 0 and np.array_equal(l_gpu, l0)
+
+
+@pytest.mark.parametrize("n,k,nrhs", [(5000, 300, 20), (3000, 40, 9), (700, 699, 4), (4097, 250, 1)])
+def test_solve_many_rhs_and_wide_bands(n, k, nrhs):
+    """Solves with more right-hand sides than one launch takes and bands wide
+    enough for the pre-accumulating helper workgroups."""
+    ab = synth.band_diagdom(n, k, 3 * n + k)
+    l_or, _ = oracle.factor(ab, k)
+    b = synth.rhs(n, nrhs, 11)
+    x = gpu_solve(l_or, k, b)
+    assert oracle.solve_residual(ab, k, x, b) <= ETA_TOL
+    x_or = oracle.solve(l_or, k, b)
+    assert np.max(np.abs(x - x_or)) <= 1e-12 * np.max(np.abs(x_or))
