@@ -33,6 +33,9 @@
 #include "common.h"
 
 size_t bandchol_solve_workspace(int64_t n);
+size_t bandchol_factor2_workspace(int64_t n, int64_t K);
+hipError_t bandchol_factor2_launch(int64_t n, int64_t k, double* ab, int64_t ldab, int64_t* d_info, void* ws,
+                                   int grid_max, hipStream_t st);
 hipError_t bandchol_solve_launch(int64_t n, int64_t k, int64_t nrhs, const double* ab, int64_t ldab, double* b,
                                  int64_t ldb, void* ws, int num_cus, hipStream_t st);
 
@@ -472,6 +475,7 @@ struct DevWork {
   void* ptr = nullptr;
   size_t size = 0;
   void* info_host = nullptr;  // pinned int64 for the synchronous calls
+  void* info_dev = nullptr;   // device int64 for the synchronous calls (never reallocated)
 };
 std::mutex g_mu;
 std::vector<DevWork> g_work;
@@ -498,18 +502,29 @@ void* workspace(size_t bytes, hipError_t* err) {
     if (*err != hipSuccess) { w.ptr = nullptr; return nullptr; }
     w.size = want;
   }
-  if (!w.info_host) {
-    *err = hipHostMalloc(&w.info_host, 64, hipHostMallocDefault);
-    if (*err != hipSuccess) { w.info_host = nullptr; return nullptr; }
-  }
   return w.ptr;
 }
 
-int64_t* info_host() {
+// Host (pinned) and device int64 slots used by the synchronous factor call to
+// return info.  They live apart from the workspace, which the launch may grow.
+bool info_slots(int64_t** h, int64_t** d, hipError_t* err) {
   int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  *err = hipGetDevice(&dev);
+  if (*err != hipSuccess) return false;
   std::lock_guard<std::mutex> lk(g_mu);
-  return (int)g_work.size() > dev ? (int64_t*)g_work[dev].info_host : nullptr;
+  if ((int)g_work.size() <= dev) g_work.resize(dev + 1);
+  DevWork& w = g_work[dev];
+  if (!w.info_host) {
+    *err = hipHostMalloc(&w.info_host, 64, hipHostMallocDefault);
+    if (*err != hipSuccess) { w.info_host = nullptr; return false; }
+  }
+  if (!w.info_dev) {
+    *err = hipMalloc(&w.info_dev, 256);
+    if (*err != hipSuccess) { w.info_dev = nullptr; return false; }
+  }
+  *h = (int64_t*)w.info_host;
+  *d = (int64_t*)w.info_dev;
+  return true;
 }
 
 inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -556,6 +571,15 @@ int walk_kmax() {
   return g_walk_kmax;
 }
 
+bool use_spine() {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = getenv("BANDCHOL_SCHEDULE");
+    v = (e && strcmp(e, "tiles") == 0) ? 0 : 1;
+  }
+  return v == 1;
+}
+
 hipError_t walk_attr(size_t lds) {
   static size_t done = 0;
   if (lds <= done) return hipSuccess;
@@ -584,6 +608,18 @@ int64_t factor_async_impl(int64_t n, int64_t k, double* ab, int64_t ldab, int64_
     if (e != hipSuccess) { set_err("walk attributes", e); return BANDCHOL_EHIP; }
     walk_single_kernel<<<1, NT, lds, st>>>(WalkSys{ab, n, kk, ldab}, L.K, d_info);
     e = hipGetLastError();
+    if (e != hipSuccess) { set_err("factor launch", e); return BANDCHOL_EHIP; }
+    return 0;
+  }
+  if (n > 0 && use_spine()) {
+    void* w2 = workspace(bandchol_factor2_workspace(n, L.K), &e);
+    if (!w2) { set_err("workspace", e); return BANDCHOL_EHIP; }
+    int grid = num_cus() * 2;
+    if (const char* cap = getenv("BANDCHOL_MAX_WG")) {
+      const long v = strtol(cap, nullptr, 10);
+      if (v > 0 && v < grid) grid = (int)v;
+    }
+    e = bandchol_factor2_launch(n, k, ab, ldab, d_info, w2, grid, st);
     if (e != hipSuccess) { set_err("factor launch", e); return BANDCHOL_EHIP; }
     return 0;
   }
@@ -660,13 +696,10 @@ int64_t bandchol_factor(int64_t n, int64_t k, double* ab, int64_t ldab) {
   if (ldab < k + 1) return -4;
   if (n == 0) return 0;
   hipError_t e;
-  const FactorLayout L = factor_layout(n, k);
-  char* ws = (char*)workspace(L.total, &e);
-  if (!ws) { set_err("workspace", e); return BANDCHOL_EHIP; }
-  int64_t* d_info = (int64_t*)(ws + 24);
+  int64_t *h = nullptr, *d_info = nullptr;
+  if (!info_slots(&h, &d_info, &e)) { set_err("info slots", e); return BANDCHOL_EHIP; }
   int64_t rc = factor_async_impl(n, k, ab, ldab, d_info, g_stream);
   if (rc != 0) return rc;
-  int64_t* h = info_host();
   e = hipMemcpyAsync(h, d_info, sizeof(int64_t), hipMemcpyDeviceToHost, g_stream);
   if (e == hipSuccess) e = hipStreamSynchronize(g_stream);
   if (e != hipSuccess) { set_err("factor", e); return BANDCHOL_EHIP; }
@@ -697,10 +730,9 @@ void bandchol_finalize(void) {
   (void)hipGetDevice(&cur);
   for (size_t d = 0; d < g_work.size(); ++d) {
     if (hipSetDevice((int)d) != hipSuccess) continue;
-    if (g_work[d].ptr) {
-      (void)hipDeviceSynchronize();
-      (void)hipFree(g_work[d].ptr);
-    }
+    (void)hipDeviceSynchronize();
+    if (g_work[d].ptr) (void)hipFree(g_work[d].ptr);
+    if (g_work[d].info_dev) (void)hipFree(g_work[d].info_dev);
     if (g_work[d].info_host) (void)hipHostFree(g_work[d].info_host);
     g_work[d] = DevWork();
   }

@@ -114,8 +114,8 @@ __device__ __forceinline__ d4 blk_gemm_lds(const lds_d* x, const lds_d* y, int b
 }
 
 // out = X_blk(bi) * L^{-T}, X in LDS (column-major), L^{-T} row-major T x T in LDS
-// (upper triangular, so k-steps past column 16*bj+15 are zero).
-__device__ __forceinline__ d4 blk_trsm_lds(const lds_d* x, const lds_d* linvt, int bi, int bj) {
+// with row pitch `pitch` (upper triangular, so k-steps past column 16*bj+15 are zero).
+__device__ __forceinline__ d4 blk_trsm_lds(const lds_d* x, const lds_d* linvt, int bi, int bj, int pitch = T) {
   const int lane = lane_id();
   d4 out = {0, 0, 0, 0};
   const int qmax = 4 * bj + 4;
@@ -123,7 +123,7 @@ __device__ __forceinline__ d4 blk_trsm_lds(const lds_d* x, const lds_d* linvt, i
   for (int q = 0; q < T / 4; ++q) {
     if (q < qmax) {
       const int kk = 4 * q + (lane >> 4);
-      out = mfma_xyt(x[kk * LP + 16 * bi + (lane & 15)], linvt[kk * T + 16 * bj + (lane & 15)], out);
+      out = mfma_xyt(x[kk * LP + 16 * bi + (lane & 15)], linvt[kk * pitch + 16 * bj + (lane & 15)], out);
     }
   }
   return out;
@@ -172,6 +172,60 @@ __device__ __forceinline__ int sweep_ldlt(double (&row)[T], lds_d* wbuf) {
     row[j] = (lane == j) ? 1.0 : q;
 #pragma unroll
     for (int l = j + 1; l < T; ++l) row[l] = fma(-q, readlane_d(w, l), row[l]);
+  }
+  const double s_mine = sqrt(d_mine);
+#pragma unroll
+  for (int c = 0; c < T; ++c) row[c] *= readlane_d(s_mine, c);
+  return fail;
+}
+
+// The same sweep, with the column broadcast through LDS instead of readlane:
+// every lane stores its w_ij, and the values w_lj (l > j) come back two at a
+// time with 16-byte broadcast reads (all lanes read the same address).  The
+// two values on the pivot chain (the next pivot and its multiplier) still use
+// readlane.  wbuf: 2 x 64 doubles of LDS, 16-byte aligned, private to the wave.
+typedef double d2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) d2 lds_d2;
+
+__device__ __forceinline__ int sweep_ldlt_lds(double (&row)[T], lds_d* wbuf) {
+  const int lane = lane_id();
+  double d_mine = 1.0;
+  double dcur = readlane_d(row[0], 0);
+  int fail = -1;
+#pragma unroll
+  for (int j = 0; j < T; ++j) {
+    lds_d* wb = wbuf + 64 * (j & 1);
+    const double d = dcur;
+    fail = (fail < 0 && !(d > 0.0)) ? j : fail;
+    const double w = row[j];
+    wb[lane] = w;
+    double p = 0.0, wn = 0.0;
+    if (j + 1 < T) {
+      p = readlane_d(row[j + 1], j + 1);
+      wn = readlane_d(w, j + 1);
+    }
+    const double dinv = recip(d);
+    d_mine = (lane == j) ? d : d_mine;
+    if (j + 1 < T) dcur = fma(-(wn * wn), dinv, p);
+    const double q = w * dinv;
+    row[j] = (lane == j) ? 1.0 : q;
+    const lds_d2* wb2 = (const lds_d2*)wb;
+#pragma unroll
+    for (int l = j + 1; l < T; ++l) {
+      double wl;
+      if ((l & 1) == 0 && l + 1 < T) {
+        const d2 v = wb2[l >> 1];
+        wl = v.x;
+        row[l + 1] = fma(-q, v.y, row[l + 1]);
+      } else if ((l & 1) == 1 && l == j + 1) {
+        wl = wb[l];
+      } else if ((l & 1) == 1) {
+        continue;  // done with its even partner
+      } else {
+        wl = wb[l];
+      }
+      row[l] = fma(-q, wl, row[l]);
+    }
   }
   const double s_mine = sqrt(d_mine);
 #pragma unroll

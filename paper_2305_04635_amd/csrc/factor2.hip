@@ -1,0 +1,556 @@
+// Multi-workgroup band Cholesky for wide bands (gfx950, FP64).
+//
+// Tiles T x T down the band, tile (R, C) for 0 <= R - C <= K.  One workgroup,
+// the spine (whoever takes ticket 0), carries the dependency chain along the
+// diagonal, one tile column per step:
+//   phase A  wave 0: factor the staged diagonal tile (register sweep) ->
+//            L(C,C) and L(C,C)^{-T}, published at once;
+//            waves 1-3: complete tile (C+1, C) and the next diagonal tile with
+//            the one term (column C-1) the helpers could not have applied yet;
+//   phase B  all waves: L(C+1, C) = tile * L(C,C)^{-T}, published;
+//   phase C  waves 1-3: next diagonal tile -= L(C+1,C) L(C+1,C)^T, staged.
+// Helper workgroups take the other tickets, in an order where every task only
+// waits for lower tickets or for spine steps:
+//   O(R, C), R - C >= 2: acc = A(R,C) - sum_s L(R,s) L(C,s)^T (terms applied as
+//            their operand tiles are published), then L(R,C) = acc L(C,C)^{-T};
+//   H(m):    the spine's two tiles of step m-1, (m, m-1) and (m, m), with every
+//            term but the last one (s <= m-3) applied, published for the spine.
+// Data between workgroups moves through relaxed agent-scope atomic loads and
+// stores (coherent across the chip without cache flushes); a flag is raised
+// after the data stores of the raising wave(s) have completed.
+#include <stdint.h>
+
+#include "common.h"
+
+namespace bandchol_f2 {
+
+using namespace bandchol;
+
+constexpr int NT = 256;
+// Bound on polls of one flag (each poll sleeps ~64 cycles plus a memory round trip);
+// far above any legitimate wait, which lasts a few spine steps.
+constexpr long long SPIN_LIMIT = 1LL << 22;
+
+typedef __attribute__((address_space(1))) int glb_i;
+
+struct Ws {
+  glb_i* tflag;     // NB*(K+1): tile (R, R-d) published, index R*(K+1)+d
+  glb_i* hflag;     // NB: pre-accumulated tiles of step m-1 published
+  glb_d* linvt;     // NB*T*T: L(C,C)^{-T}, row-major
+  glb_d* pre;       // NB*2*T*T: per m, tile (m,m-1) then tile (m,m), column-major
+  unsigned* queue;
+  glb_i* abort_flag;  // 1 = pivot failure, 2 = wait bound exceeded
+  unsigned long long* first_fail;
+};
+
+struct Args {
+  Band a;
+  int NB, K;
+  unsigned ntickets;
+  Ws w;
+};
+
+__device__ __forceinline__ double aload(const glb_d* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void astore(glb_d* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int aflag(const glb_i* p) {
+  return __builtin_amdgcn_readfirstlane(__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ void raise_flag(glb_i* p) { __hip_atomic_store(p, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+
+// A lane's run of band elements A(i, j0 + cs*q), q = 0, 1, ...: the first at p,
+// the next ones cs*(ldab-1) doubles apart (A(i, j) sits at ab + i + j*(ldab-1)).
+// Element q is in the band iff i < n and 0 <= d0 - cs*q <= k.  Set up once per
+// tile so that each element costs one compare and one pointer step.
+struct Run {
+  glb_d* p;
+  int64_t step;
+  int d0, ds, k;
+  bool row_ok;
+  __device__ __forceinline__ bool in(int q) const {
+    const int d = d0 - ds * q;
+    return row_ok && d >= 0 && d <= k;
+  }
+  __device__ __forceinline__ glb_d* at(int q) const { return p + step * q; }
+  __device__ __forceinline__ double ld(int q) const { return in(q) ? aload(at(q)) : 0.0; }
+};
+
+__device__ __forceinline__ Run band_run(const Band& a, int64_t i, int64_t j0, int cs) {
+  Run r;
+  r.p = a.ab + i + j0 * (a.ldab - 1);
+  r.step = (int64_t)cs * (a.ldab - 1);
+  r.d0 = (int)(i - j0);
+  r.ds = cs;
+  r.k = (int)(a.k < 0x7fffffff ? a.k : 0x7fffffff);
+  r.row_ok = i < a.n;
+  return r;
+}
+
+// This wave waits for *f (bounded); every lane gets the same answer.
+__device__ __forceinline__ bool wave_wait(const glb_i* f, const Ws& w) {
+  glb_i* const abort_flag = w.abort_flag;
+  long long spins = 0;
+  while (!aflag(f)) {
+    if (aflag(abort_flag)) return false;
+    if (++spins > SPIN_LIMIT) {
+      __hip_atomic_store(abort_flag, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");  // keeps later loads below the wait
+  return true;
+}
+
+__device__ __forceinline__ int tidx(const Args& A, int64_t R, int64_t C) { return (int)(R * (A.K + 1) + (R - C)); }
+
+// ---------------------------------------------------------------- block I/O with atomics
+
+// Block (bi, bj) of tile (R, C) in accumulator form (see common.h).  On a
+// diagonal tile the positions past row n-1 get an identity.
+__device__ __forceinline__ d4 ablk_load(const Band& a, int64_t R, int64_t C, int bi, int bj) {
+  const int lane = lane_id();
+  const Run run = band_run(a, R * T + 16 * bi + (lane & 15), C * T + 16 * bj + (lane >> 4), 4);
+  d4 acc;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    double v = run.ld(r);
+    if (R == C && !run.row_ok && run.d0 - 4 * r == 0) v = 1.0;
+    acc[r] = v;
+  }
+  return acc;
+}
+
+__device__ __forceinline__ void ablk_store(const Band& a, int64_t R, int64_t C, int bi, int bj, d4 v) {
+  const int lane = lane_id();
+  const Run run = band_run(a, R * T + 16 * bi + (lane & 15), C * T + 16 * bj + (lane >> 4), 4);
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    if (run.in(r)) astore(run.at(r), v[r]);
+}
+
+// A dense T x T tile in column-major workspace memory.
+__device__ __forceinline__ d4 wblk_load(const glb_d* t, int bi, int bj) {
+  const int lane = lane_id();
+  d4 v;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) v[r] = aload(t + (16 * bj + 4 * r + (lane >> 4)) * T + 16 * bi + (lane & 15));
+  return v;
+}
+__device__ __forceinline__ void wblk_store(glb_d* t, int bi, int bj, d4 v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) astore(t + (16 * bj + 4 * r + (lane >> 4)) * T + 16 * bi + (lane & 15), v[r]);
+}
+
+// acc -= X_blk(bi) Y_blk(bj)^T with X = tile (Rx, s), Y = tile (Ry, s) from the band.
+__device__ __forceinline__ d4 aterm(const Band& a, int64_t Rx, int64_t Ry, int64_t s, int bi, int bj, d4 acc) {
+  const int lane = lane_id();
+  const int64_t j0 = s * T + (lane >> 4);
+  const Run x = band_run(a, Rx * T + 16 * bi + (lane & 15), j0, 4);
+  const Run y = band_run(a, Ry * T + 16 * bj + (lane & 15), j0, 4);
+  double xf[T / 4], yf[T / 4];
+#pragma unroll
+  for (int q = 0; q < T / 4; ++q) {
+    xf[q] = x.ld(q);
+    yf[q] = y.ld(q);
+  }
+#pragma unroll
+  for (int q = 0; q < T / 4; ++q) acc = mfma_xyt(-xf[q], yf[q], acc);
+  return acc;
+}
+
+// ---------------------------------------------------------------- helpers
+
+// Apply the terms s in [s0, s1) of tile (R, C) (blocks of this wave), in runs
+// of published operand tiles.  Xrow = R, Yrow = C.
+__device__ __forceinline__ bool apply_terms(const Args& A, int64_t R, int64_t C, int64_t s0, int64_t s1, int bi, int bj, d4& acc) {
+  for (int64_t s = s0; s < s1; ++s) {
+    // operands: tile (R, s) and tile (C, s); spine tiles (d = 1) and helper tiles share one flag array
+    if (!wave_wait(&A.w.tflag[tidx(A, R, s)], A.w)) return false;
+    if (C != R && !wave_wait(&A.w.tflag[tidx(A, C, s)], A.w)) return false;
+    acc = aterm(A.a, R, C, s, bi, bj, acc);
+  }
+  return true;
+}
+
+// Trsm of the accumulator tile held across the 4 waves: out = acc * L(C,C)^{-T}.
+__device__ __forceinline__ d4 trsm_from_lds(const lds_d* x, const glb_d* linvt_g, int bi, int bj) {
+  const int lane = lane_id();
+  d4 out = {0, 0, 0, 0};
+  const int qmax = 4 * bj + 4;
+  double yf[T / 4];
+#pragma unroll
+  for (int q = 0; q < T / 4; ++q) yf[q] = (q < qmax) ? aload(linvt_g + (4 * q + (lane >> 4)) * T + 16 * bj + (lane & 15)) : 0.0;
+#pragma unroll
+  for (int q = 0; q < T / 4; ++q)
+    if (q < qmax) out = mfma_xyt(x[(4 * q + (lane >> 4)) * LP + 16 * bi + (lane & 15)], yf[q], out);
+  return out;
+}
+
+// The noinline functions below copy their structure arguments into locals
+// first: the references point at a stack copy, and after every atomic store or
+// fence the fields would otherwise be re-read from memory.
+__device__ __attribute__((noinline)) void task_off(const Args& A_, int64_t R, int64_t C, lds_d* stage, lds_i* s_ok) {
+  const Args A = A_;
+  const int wave = wave_id();
+  const int bi = wave & 1, bj = wave >> 1;
+  d4 acc = ablk_load(A.a, R, C, bi, bj);
+  const int64_t s0 = R - A.K > 0 ? R - A.K : 0;
+  int ok = apply_terms(A, R, C, s0, C, bi, bj, acc) ? 1 : 0;
+  if (ok) ok = wave_wait(&A.w.tflag[tidx(A, C, C)], A.w) ? 1 : 0;
+  blk_to_lds(stage, bi, bj, acc);
+  if (!ok && lane_id() == 0) *s_ok = 0;
+  __syncthreads();
+  if (*s_ok == 0) return;
+  const d4 out = trsm_from_lds(stage, A.w.linvt + C * T * T, bi, bj);
+  ablk_store(A.a, R, C, bi, bj, out);
+  wait_vmem();
+  __syncthreads();
+  if (threadIdx.x == 0) raise_flag(&A.w.tflag[tidx(A, R, C)]);
+}
+
+// Pre-accumulate the spine's tiles of step m-1: (m, m-1) and (m, m), terms s <= m-3.
+__device__ __attribute__((noinline)) void task_pre(const Args& A_, int64_t m, lds_i* s_ok) {
+  const Args A = A_;
+  const int wave = wave_id();
+  const int64_t s0 = m - A.K > 0 ? m - A.K : 0;
+  glb_d* po = A.w.pre + m * 2 * T * T;
+  glb_d* pd = po + T * T;
+  // waves 0-3: one block of (m, m-1) each; waves 1-3 also one lower block of
+  // (m, m).  Both blocks of a wave take each term as soon as its operands are
+  // published, so that only the last term is left once the last one arrives.
+  int ok = 1;
+  const int bi = wave & 1, bj = wave >> 1;
+  const int di = (wave >= 2), dj = (wave == 3);
+  d4 acc = ablk_load(A.a, m, m - 1, bi, bj);
+  d4 accd = {0, 0, 0, 0};
+  if (wave >= 1) accd = ablk_load(A.a, m, m, di, dj);
+  for (int64_t s = s0; s < m - 2; ++s) {
+    if (!wave_wait(&A.w.tflag[tidx(A, m, s)], A.w) || !wave_wait(&A.w.tflag[tidx(A, m - 1, s)], A.w)) {
+      ok = 0;
+      break;
+    }
+    acc = aterm(A.a, m, m - 1, s, bi, bj, acc);
+    if (wave >= 1) accd = aterm(A.a, m, m, s, di, dj, accd);
+  }
+  wblk_store(po, bi, bj, acc);
+  if (wave >= 1) wblk_store(pd, di, dj, accd);
+  if (!ok && lane_id() == 0) *s_ok = 0;
+  wait_vmem();
+  __syncthreads();
+  if (*s_ok == 0) return;
+  if (threadIdx.x == 0) raise_flag(&A.w.hflag[m]);
+}
+
+// ---------------------------------------------------------------- spine
+
+struct SpineLds {
+  lds_d* diag;    // staged diagonal tile (column-major, LP)
+  lds_d* acco;    // staged tile (C+1, C)
+  lds_d* accd;    // next diagonal tile before its last update
+  lds_d* lcur;    // L(C+1, C)
+  lds_d* lprev;   // L(C, C-1)
+  lds_d* linvt;   // L(C,C)^{-T}, row-major, row pitch LP
+  lds_d* lcc;     // L(C,C) (column-major, LP)
+};
+
+__device__ __attribute__((noinline)) void spine_sweep(const Args& A_, int64_t C, const SpineLds& S_, lds_i* s_fail) {
+  const Args A = A_;
+  const SpineLds S = S_;
+  const int lane = lane_id();
+  const Band& a = A.a;
+  double row[T];
+#pragma unroll
+  for (int c = 0; c < T; ++c) row[c] = lane < T ? S.diag[c * LP + lane] : ((lane - T) == c ? 1.0 : 0.0);
+  const int fail = sweep_ldlt(row, nullptr);
+  if (fail >= 0) {
+    if (lane == 0) {
+      *s_fail = fail;
+      const long long col = (long long)C * T + fail;
+      if (col < a.n) atomicMin(A.w.first_fail, (unsigned long long)(col + 1));
+      __hip_atomic_store(A.w.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return;
+  }
+  // L(C,C) and L(C,C)^{-T} go to LDS only (both conflict-free: pitch LP);
+  // another wave copies them to global memory off the critical path.
+#pragma unroll
+  for (int c = 0; c < T; ++c) {
+    if (lane < T) S.lcc[c * LP + lane] = row[c];
+    else S.linvt[(lane - T) * LP + c] = row[c];
+  }
+}
+
+// One wave copies the spine's results of step C from LDS to global memory with
+// coalesced stores: L(C,C) (lower triangle), L(C,C)^{-T} (row-major, for the
+// helpers' trsm) and, if `off`, L(C+1, C) from `lcur`.  Does not wait for them.
+__device__ __attribute__((noinline)) void spine_publish(const Args& A_, int64_t C, const SpineLds& S_, const lds_d* lcur,
+                                                        bool off) {
+  const Args A = A_;
+  const SpineLds S = S_;
+  const Band& a = A.a;
+  const int lane = lane_id();
+  const int r = lane & 31;
+  glb_d* lt = A.w.linvt + C * T * T;
+  // all LDS reads first, then the stores (a store waiting on its own read
+  // would serialise the LDS latency)
+  double vl[T / 2], vt[T / 2], vo[T / 2];
+#pragma unroll
+  for (int p = 0; p < T / 2; ++p) {
+    const int c = 2 * p + (lane >> 5);
+    const int e = 64 * p + lane;
+    vl[p] = S.lcc[c * LP + r];
+    vt[p] = S.linvt[(e / T) * LP + (e % T)];
+    vo[p] = off ? lcur[c * LP + r] : 0.0;
+  }
+  // lane (r, h) stores column 2p + h of rows r of tiles (C, C) and (C+1, C)
+  const Run rd = band_run(a, C * T + r, C * T + (lane >> 5), 2);
+#pragma unroll
+  for (int p = 0; p < T / 2; ++p)
+    if (rd.in(p)) astore(rd.at(p), vl[p]);
+#pragma unroll
+  for (int p = 0; p < T / 2; ++p) astore(lt + 64 * p + lane, vt[p]);
+  if (off) {
+    const Run ro = band_run(a, (C + 1) * T + r, C * T + (lane >> 5), 2);
+#pragma unroll
+    for (int p = 0; p < T / 2; ++p)
+      if (ro.in(p)) astore(ro.at(p), vo[p]);
+  }
+}
+
+// waves 1-3: tiles (C+1, C) and (C+1, C+1) with everything but the critical
+// update.  The 7 lower blocks (4 of (m, C), 3 of (m, m)) go to waves 1-3 as
+// b = wave-1, wave+2, wave+5.  The term s = C-1 uses X = L(m, C-1) for both
+// tiles, Y = L(C, C-1) (staged in LDS) for (m, C) and Y = L(m, C-1) for (m, m);
+// every global load is issued before the first MFMA.
+__device__ __attribute__((noinline)) void spine_prepare(const Args& A_, int64_t C, const SpineLds& S_, lds_i* s_fail) {
+  const Args A = A_;
+  const SpineLds S = S_;
+  const int wave = wave_id();
+  const int lane = lane_id();
+  const int64_t m = C + 1;
+  const bool have_pre = A.K >= 3 && m >= 3;
+  const glb_d* po = A.w.pre + m * 2 * T * T;
+  const glb_d* pd = po + T * T;
+  if (have_pre && !wave_wait(&A.w.hflag[m], A.w)) { if (lane == 0) *s_fail = -2; return; }
+  // term s = C-1 needs L(m, C-1) (a helper tile) and L(C, C-1) (S.lprev)
+  const bool t1 = C >= 1 && A.K >= 2;
+  if (t1 && !wave_wait(&A.w.tflag[tidx(A, m, C - 1)], A.w)) { if (lane == 0) *s_fail = -2; return; }
+  d4 acc[3];
+  double x0[T / 4], x1[T / 4];  // fragments of L(m, C-1), rows 0-15 and 16-31
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    const int b = wave - 1 + 3 * u;
+    acc[u] = d4{0, 0, 0, 0};
+    if (b < 4) {
+      const int bi = b & 1, bj = b >> 1;
+      acc[u] = have_pre ? wblk_load(po, bi, bj) : ablk_load(A.a, m, C, bi, bj);
+    } else if (b < 7) {
+      const int bi = (b >= 5), bj = (b == 6);
+      acc[u] = have_pre ? wblk_load(pd, bi, bj) : ablk_load(A.a, m, m, bi, bj);
+    }
+  }
+  if (t1) {
+    const int64_t j0 = (C - 1) * T + (lane >> 4);
+    const Run r0 = band_run(A.a, m * T + (lane & 15), j0, 4);
+    const Run r1 = band_run(A.a, m * T + 16 + (lane & 15), j0, 4);
+#pragma unroll
+    for (int q = 0; q < T / 4; ++q) {
+      x0[q] = r0.ld(q);
+      x1[q] = r1.ld(q);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    const int b = wave - 1 + 3 * u;
+    if (b < 4) {
+      const int bi = b & 1, bj = b >> 1;
+      if (t1) {
+#pragma unroll
+        for (int q = 0; q < T / 4; ++q)
+          acc[u] = mfma_xyt(-(bi ? x1[q] : x0[q]), S.lprev[(4 * q + (lane >> 4)) * LP + 16 * bj + (lane & 15)], acc[u]);
+      }
+      blk_to_lds(S.acco, bi, bj, acc[u]);
+    } else if (b < 7) {
+      const int bi = (b >= 5), bj = (b == 6);
+      if (t1) {
+#pragma unroll
+        for (int q = 0; q < T / 4; ++q) acc[u] = mfma_xyt(-(bi ? x1[q] : x0[q]), bj ? x1[q] : x0[q], acc[u]);
+      }
+      blk_to_lds(S.accd, bi, bj, acc[u]);
+    }
+  }
+}
+
+__device__ void spine(const Args& A, lds_d* base, lds_i* s_fail) {
+  const int wave = wave_id();
+  const Band& a = A.a;
+  SpineLds S;
+  S.diag = base;
+  S.acco = S.diag + T * LP;
+  S.accd = S.acco + T * LP;
+  S.lcur = S.accd + T * LP;
+  S.lprev = S.lcur + T * LP;
+  S.linvt = S.lprev + T * LP;
+  S.lcc = S.linvt + T * LP;
+  if (threadIdx.x == 0) *s_fail = -1;
+  // stage tile (0,0)
+  if (wave >= 1) {
+    const int bi = (wave >= 2), bj = (wave == 3);
+    blk_to_lds(S.diag, bi, bj, ablk_load(a, 0, 0, bi, bj));
+  } else {
+    blk_to_lds(S.diag, 0, 1, d4{0, 0, 0, 0});
+  }
+  __syncthreads();
+  for (int64_t C = 0; C < A.NB; ++C) {
+    const bool next = C + 1 < A.NB;
+    // results of step C-1 published by wave 1 in its phase C: drain, then flag
+    if (wave == 1 && C >= 1) {
+      wait_vmem();
+      if (lane_id() == 0) {
+        raise_flag(&A.w.tflag[tidx(A, C - 1, C - 1)]);
+        if (A.K >= 1) raise_flag(&A.w.tflag[tidx(A, C, C - 1)]);
+      }
+    }
+    // phase A
+    if (wave == 0) spine_sweep(A, C, S, s_fail);
+    else if (next && A.K >= 1) spine_prepare(A, C, S, s_fail);
+    else if (next && wave >= 1) {
+      const int bi = (wave >= 2), bj = (wave == 3);
+      blk_to_lds(S.accd, bi, bj, ablk_load(a, C + 1, C + 1, bi, bj));
+    }
+    __syncthreads();
+    if (*s_fail != -1) return;
+    if (!next) {
+      if (wave == 1) spine_publish(A, C, S, S.lcur, false);
+      return;
+    }
+    // phase B: L(C+1, C) = acco * L(C,C)^{-T}, into LDS
+    if (A.K >= 1) {
+      const int bi = wave & 1, bj = wave >> 1;
+      blk_to_lds(S.lcur, bi, bj, blk_trsm_lds(S.acco, S.linvt, bi, bj, LP));
+    }
+    __syncthreads();
+    // phase C: next diagonal tile (waves 0, 2, 3); wave 1 publishes step C
+    if (wave == 1) {
+      spine_publish(A, C, S, S.lcur, A.K >= 1);
+    } else {
+      const int bi = (wave >= 2), bj = (wave == 3);
+      d4 acc = {0, 0, 0, 0};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] = S.accd[(16 * bj + 4 * r + (lane_id() >> 4)) * LP + 16 * bi + (lane_id() & 15)];
+      if (A.K >= 1) acc = blk_gemm_lds(S.lcur, S.lcur, bi, bj, acc);
+      blk_to_lds(S.diag, bi, bj, acc);
+      if (wave == 0) blk_to_lds(S.diag, 0, 1, d4{0, 0, 0, 0});
+    }
+    lds_d* t = S.lprev; S.lprev = S.lcur; S.lcur = t;
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- kernel
+
+// Ticket order: 0 = spine; then per column C: O(C+2..C+K, C), then H(C+3).
+__host__ __device__ __forceinline__ unsigned tickets_per_column(int K) {
+  return K >= 2 ? (unsigned)(K - 1) + (K >= 3 ? 1u : 0u) : 0u;
+}
+
+__device__ __forceinline__ void decode(const Args& A, unsigned t, int& kind, int64_t& R, int64_t& C) {
+  const unsigned per = tickets_per_column(A.K);
+  const unsigned u = t - 1;
+  C = u / per;
+  const unsigned slot = u % per;
+  if (slot < (unsigned)(A.K - 1)) {
+    kind = 1;
+    R = C + 2 + slot;
+  } else {
+    kind = 2;
+    R = C + 3;
+  }
+}
+
+__global__ void __launch_bounds__(NT) factor2_kernel(Args A) {
+  __shared__ double lds[7 * T * LP];
+  __shared__ int s_ticket, s_ok, s_abort;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      s_ticket = (int)atomicAdd(A.w.queue, 1u);
+      s_abort = aflag(A.w.abort_flag);
+    }
+    __syncthreads();
+    const unsigned t = (unsigned)s_ticket;
+    const int stop = s_abort;
+    __syncthreads();
+    if (threadIdx.x == 0) s_ok = 1;
+    __syncthreads();
+    if (t >= A.ntickets || stop) break;
+    if (t == 0) {
+      spine(A, (lds_d*)lds, (lds_i*)&s_ok);
+    } else {
+      int kind;
+      int64_t R, C;
+      decode(A, t, kind, R, C);
+      if (R < A.NB) {
+        if (kind == 1) task_off(A, R, C, (lds_d*)lds, (lds_i*)&s_ok);
+        else task_pre(A, R, (lds_i*)&s_ok);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void factor2_init(glb_i* flags, int64_t count, unsigned* queue, glb_i* abort_flag, unsigned long long* ff) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t x = g; x < count; x += (int64_t)gridDim.x * blockDim.x) flags[x] = 0;
+  if (g == 0) { *queue = 0; *abort_flag = 0; *ff = 0x7fffffffffffffffULL; }
+}
+
+__global__ void factor2_finish(const glb_i* abort_flag, const unsigned long long* ff, int64_t* d_info) {
+  const int ab = *abort_flag;
+  const unsigned long long f = *ff;
+  *d_info = (ab == 2) ? (int64_t)-1001 : (f == 0x7fffffffffffffffULL ? 0 : (int64_t)f);
+}
+
+}  // namespace bandchol_f2
+
+// Workspace bytes for n, k (K = sub-diagonal tile count).
+size_t bandchol_factor2_workspace(int64_t n, int64_t K) {
+  using namespace bandchol_f2;
+  const int64_t NB = (n + T - 1) / T;
+  const size_t flags = sizeof(int) * (size_t)(NB * (K + 1) + NB);
+  return 256 + ((flags + 255) & ~(size_t)255) + sizeof(double) * (size_t)NB * T * T * 3;
+}
+
+hipError_t bandchol_factor2_launch(int64_t n, int64_t k, double* ab, int64_t ldab, int64_t* d_info, void* ws,
+                                   int grid_max, hipStream_t st) {
+  using namespace bandchol_f2;
+  const int NB = (int)((n + T - 1) / T);
+  int K = (int)((k + T - 1) / T);
+  if (K > NB - 1) K = NB - 1 > 0 ? NB - 1 : 0;
+  char* base = (char*)ws;
+  Args A;
+  A.a = Band{(glb_d*)ab, n, k, ldab};
+  A.NB = NB;
+  A.K = K;
+  A.w.queue = (unsigned*)base;
+  A.w.abort_flag = (glb_i*)(base + 8);
+  A.w.first_fail = (unsigned long long*)(base + 16);
+  A.w.tflag = (glb_i*)(base + 256);
+  A.w.hflag = A.w.tflag + (size_t)NB * (K + 1);
+  const size_t flags = sizeof(int) * (size_t)(NB * (K + 1) + NB);
+  A.w.linvt = (glb_d*)(base + 256 + ((flags + 255) & ~(size_t)255));
+  A.w.pre = A.w.linvt + (size_t)NB * T * T;
+  A.ntickets = 1 + tickets_per_column(K) * (unsigned)NB;
+  const int64_t nflags = (int64_t)NB * (K + 1) + NB;
+  factor2_init<<<(unsigned)((nflags + 255) / 256 > 1024 ? 1024 : (nflags + 255) / 256 + 1), 256, 0, st>>>(
+      A.w.tflag, nflags, A.w.queue, A.w.abort_flag, A.w.first_fail);
+  int grid = grid_max;
+  if ((unsigned)grid > A.ntickets) grid = (int)A.ntickets;
+  factor2_kernel<<<grid, NT, 0, st>>>(A);
+  factor2_finish<<<1, 1, 0, st>>>(A.w.abort_flag, A.w.first_fail, d_info);
+  return hipGetLastError();
+}

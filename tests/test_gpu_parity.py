@@ -162,3 +162,17 @@ def test_solve_many_rhs_and_wide_bands(n, k, nrhs):
     assert oracle.solve_residual(ab, k, x, b) <= ETA_TOL
     x_or = oracle.solve(l_or, k, b)
     assert np.max(np.abs(x - x_or)) <= 1e-12 * np.max(np.abs(x_or))
+
+
+def test_sync_factor_workspace_growth():
+    """A synchronous factor whose launch has to grow the library's workspace
+    (info once lived inside the workspace and was read back from the freed
+    buffer after the growth)."""
+    import paper_2305_04635_amd as bc
+    bc.finalize()
+    for n, k in ((300, 100), (5000, 120), (20000, 300)):
+        ab = synth.band_diagdom(n, k, n + k)
+        l_gpu, info = gpu_factor(ab, k)
+        assert info == 0
+        rows = [(0, min(n, 96)), (n - min(n, 96), n)]
+        assert oracle.llt_residual(l_gpu, ab, k, rows=rows) <= ETA_TOL
