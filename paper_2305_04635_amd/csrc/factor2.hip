@@ -473,7 +473,7 @@ __device__ __forceinline__ void decode(const Args& A, unsigned t, int& kind, int
   }
 }
 
-__global__ void __launch_bounds__(NT) factor2_kernel(Args A) {
+__global__ void __launch_bounds__(NT, 2) factor2_kernel(Args A) {
   __shared__ double lds[7 * T * LP];
   __shared__ int s_ticket, s_ok, s_abort;
   for (;;) {
