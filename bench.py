@@ -11,6 +11,12 @@ value = sum_k [n(k^2+3k) + 4 n k nrhs] / (wall time of one step): factor and
 solve flops over the whole step, restores included.  The factor rate per k is
 reported separately from HIP events on the launch stream.
 
+--workload batched: 512 independent systems, n ~ U{1000..20000}, k ~ U{32..256}
+(diagonally dominant recipe), nrhs = 4, factored and solved by one plan whose
+factor + solve launches are captured once in a HIP graph; each step replays it
+(bands and right-hand sides restored before each replay, outside the timed
+region).  value = sum_i [n_i(k_i^2+3k_i) + 4 n_i k_i nrhs] / replay time.
+
 Prints ONE JSON line.  N > 1 GPUs is refused: this build runs on one GPU.
 """
 import argparse
@@ -95,6 +101,8 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=10000, help="rows per matrix for the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", action="store_true", help="sampled backward-error check after timing")
+    ap.add_argument("--workload", choices=("sweep", "batched"), default="sweep")
+    ap.add_argument("--batch", type=int, default=512)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -108,6 +116,8 @@ def main():
     import synth
     import paper_2305_04635_amd as bc
 
+    if args.workload == "batched":
+        return bench_batched(args)
     ks = [int(x) for x in args.ks.split(",")]
     n, nrhs = args.n, args.nrhs
     dev = torch.device("cuda:0")
@@ -227,6 +237,119 @@ def main():
         line["check"] = check
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(ks, args.cpu_rows, args.seed)
+    print(json.dumps(line))
+
+
+def batch_shapes(batch, seed):
+    """n ~ U{1000..20000}, k ~ U{32..256}, from the shared seeded generator."""
+    import synth
+    nv, kv = synth.batch_shapes(batch, seed, 1000, 20000, 32, 256)
+    return [int(x) for x in nv], [int(x) for x in kv]
+
+
+def cpu_baseline_batched(ns, ks, nrhs, seed, budget_s=12.0):
+    """The oracle (one thread) factoring and solving the first systems of the batch until
+    about budget_s seconds of CPU time have been spent."""
+    import oracle
+    import synth
+    tot_flops, tot_t, cnt = 0.0, 0.0, 0
+    for i, (n, k) in enumerate(zip(ns, ks)):
+        ab = synth.band_diagdom(n, k, seed + i)
+        b = synth.rhs(n, nrhs, seed + i)
+        t0 = time.perf_counter()
+        l, info = oracle.factor(ab, k)
+        oracle.solve(l, k, b)
+        tot_t += time.perf_counter() - t0
+        assert info == 0
+        tot_flops += factor_flops(n, k) + solve_flops(n, k, nrhs)
+        cnt += 1
+        if tot_t > budget_s:
+            break
+    return {"value": round(tot_flops / tot_t / 1e9, 4), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+            "sample": "factor + solve of the first %d systems of the batch (same shapes and recipe), "
+                      "%.1f s of CPU time" % (cnt, tot_t)}
+
+
+def bench_batched(args):
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2305_04635_amd as bc
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    bc.load()
+    nrhs = 4
+    ns, ks = batch_shapes(args.batch, args.seed)
+    t_gen = time.perf_counter()
+    ab0, b0, abs_d, bs_d = [], [], [], []
+    for i, (n, k) in enumerate(zip(ns, ks)):
+        ab = synth.band_diagdom(n, k, args.seed + i)
+        b = synth.rhs(n, nrhs, args.seed + i)
+        ab0.append(torch.from_numpy(ab.ravel(order="F")).to(dev))
+        b0.append(torch.from_numpy(np.asarray(b).ravel(order="F")).to(dev))
+        abs_d.append(torch.empty_like(ab0[-1]))
+        bs_d.append(torch.empty_like(b0[-1]))
+    t_gen = time.perf_counter() - t_gen
+    plan = bc.BatchPlan(ns, ks, abs_d, bs_d)
+    info = torch.zeros(len(ns), dtype=torch.int64, device=dev)
+
+    def restore():
+        torch._foreach_copy_(abs_d, ab0)
+        torch._foreach_copy_(bs_d, b0)
+
+    def run():
+        plan.factor(info)
+        plan.solve(nrhs)
+
+    restore()
+    run()   # eager once (sets kernel attributes), then capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        run()
+    times = []
+    for s in range(args.warmup + args.steps):
+        restore()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        if s >= args.warmup:
+            times.append(e0.elapsed_time(e1))
+    infos = info.cpu().tolist()
+    if any(x != 0 for x in infos):
+        print("bench.py: batched factorization failed: %s" % [x for x in infos if x], file=sys.stderr)
+        sys.exit(1)
+    check = None
+    if args.check:
+        import oracle
+        worst = 0.0
+        for i in range(0, len(ns), max(1, len(ns) // 16)):
+            ab = synth.band_diagdom(ns[i], ks[i], args.seed + i)
+            l = abs_d[i].cpu().numpy().reshape(ab.shape, order="F")
+            worst = max(worst, oracle.llt_residual(l, ab, ks[i]))
+        check = {"backward_error_max_of_16_systems": worst}
+    ms = float(np.median(times))
+    flops = sum(factor_flops(n, k) + solve_flops(n, k, nrhs) for n, k in zip(ns, ks))
+    value = flops / (ms * 1e-3) / 1e9
+    line = {
+        "metric": "batched band Cholesky factor+solve GFLOP/s (512 systems, n~U[1000,20000], k~U[32,256], nrhs=4)",
+        "value": round(value, 3), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "batched band Cholesky factor + solve, %d systems, diagonally dominant SPD, "
+                               "one HIP graph replay per step" % len(ns),
+                   "batch": len(ns), "nrhs": nrhs, "sum_n": sum(ns), "flops_per_step": flops,
+                   "replay_ms_min": round(min(times), 4), "input_generation_s": round(t_gen, 2)},
+    }
+    if check is not None:
+        line["check"] = check
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_batched(ns, ks, nrhs, args.seed)
+    plan.close()
     print(json.dumps(line))
 
 

@@ -103,6 +103,47 @@ int64_t bandchol_tile(void);
  */
 int64_t bandchol_set_walk_limit(int64_t kmax);
 
+/*
+ * Batches of independent systems of different orders and bandwidths.  The
+ * paper's method factors one band at a time; a single band only offers the
+ * parallelism of its own tile columns (Section 6 notes how little there is at
+ * small bandwidths), so many independent systems are run at once: one
+ * workgroup per system, every workgroup taking the next system from an atomic
+ * counter, longest first (the estimate is (n / T) * (10 + K^2) with K the
+ * number of sub-diagonal tiles).  Systems with more than 15 sub-diagonal
+ * tiles (k > 480) are factored one after another with the multi-workgroup
+ * schedule instead.
+ *
+ * bandchol_batch_create builds a plan.  All array arguments are HOST arrays of
+ * length `batch`; ab[i] and b[i] are DEVICE pointers owned by the caller and
+ * must stay valid while the plan is used:
+ *   batch >= 0 (-1); n[i] >= 0 (-2); k[i] >= 0 (-3); ab[i] != NULL when
+ *   n[i] > 0 (-4); ldab[i] >= k[i] + 1 (-5); b may be NULL (no solves),
+ *   else b[i] != NULL when n[i] > 0 (-6) and ldb[i] >= max(1, n[i]) (-7);
+ *   plan != NULL (-8).
+ * It allocates device memory (descriptors and the inverses of all diagonal
+ * tiles, 8 T^2 bytes per tile column of every system) on the current device,
+ * synchronously.  The factor and solve calls below allocate nothing and only
+ * launch kernels on `stream`, so they may be captured into a HIP graph and
+ * replayed; the plan must be destroyed only after its work has finished.
+ *
+ * bandchol_batch_factor factors every system in place and writes info per
+ * system (as for bandchol_factor) to d_info[0 .. batch-1], a DEVICE int64
+ * array.  bandchol_batch_solve(nrhs) overwrites b[i] (n[i] x nrhs,
+ * column-major) with the solution, using the factors and the inverses of the
+ * diagonal tiles left by the last bandchol_batch_factor on the same plan; call
+ * it only for systems whose info was 0.  Returns -1 for nrhs < 0, -2 when
+ * the plan has no right-hand sides.
+ */
+typedef struct bandchol_batch* bandchol_batch_t;
+
+int64_t bandchol_batch_create(int64_t batch, const int64_t* n, const int64_t* k, double* const* ab,
+                              const int64_t* ldab, double* const* b, const int64_t* ldb, bandchol_batch_t* plan);
+int64_t bandchol_batch_factor(bandchol_batch_t plan, int64_t* d_info, void* stream);
+int64_t bandchol_batch_solve(bandchol_batch_t plan, int64_t nrhs, void* stream);
+/* Frees the plan's device memory (waits for the device first). */
+void bandchol_batch_destroy(bandchol_batch_t plan);
+
 #ifdef __cplusplus
 }
 #endif

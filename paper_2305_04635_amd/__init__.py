@@ -31,6 +31,10 @@ SIGNATURES = {
     "bandchol_finalize": (None, []),
     "bandchol_tile": (_I64, []),
     "bandchol_set_walk_limit": (_I64, [_I64]),
+    "bandchol_batch_create": (_I64, [_I64, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "bandchol_batch_factor": (_I64, [_VP, _VP, _VP]),
+    "bandchol_batch_solve": (_I64, [_VP, _I64, _VP]),
+    "bandchol_batch_destroy": (None, [_VP]),
 }
 
 EHIP = -1000
@@ -132,6 +136,70 @@ def solve_async(ab, n, k, b, nrhs=None, ldab=None, ldb=None):
     rc = load().bandchol_solve_async(n, k, nrhs, ab.data_ptr(), ldab, b.data_ptr(), ldb, _stream())
     if rc != 0:
         _raise(rc, "bandchol_solve_async")
+
+
+class BatchPlan:
+    """Batch of independent band systems (``bandchol_batch_*``).
+
+    ``abs``: list of float64 GPU tensors holding the bands (LAPACK lower layout,
+    ldab = k+1 unless ``ldabs`` is given); ``bs``: optional list of float64 GPU
+    tensors for the right-hand sides (n x nrhs column-major, ldb = n).  The
+    tensors must stay alive as long as the plan.  ``factor`` and ``solve``
+    only launch kernels on the current stream (they can be captured in a
+    ``torch.cuda.CUDAGraph``).
+    """
+
+    def __init__(self, ns, ks, abs, bs=None, ldabs=None):
+        batch = len(ns)
+        if len(ks) != batch or len(abs) != batch or (bs is not None and len(bs) != batch):
+            raise ValueError("ns, ks, abs and bs must have the same length")
+        for t in abs:
+            _check_tensor(t, "ab")
+        if bs is not None:
+            for t in bs:
+                _check_tensor(t, "b")
+        ldabs = [k + 1 for k in ks] if ldabs is None else list(ldabs)
+        I64 = ctypes.c_int64 * max(batch, 1)
+        PTR = ctypes.c_void_p * max(batch, 1)
+        self._n = I64(*ns)
+        self._k = I64(*ks)
+        self._ldab = I64(*ldabs)
+        self._ab = PTR(*[t.data_ptr() for t in abs])
+        self._b = PTR(*[t.data_ptr() for t in bs]) if bs is not None else None
+        self._ldb = I64(*[max(n, 1) for n in ns]) if bs is not None else None
+        self._keep = (list(abs), list(bs) if bs is not None else None)
+        self.batch = batch
+        self._plan = ctypes.c_void_p()
+        rc = load().bandchol_batch_create(batch, self._n, self._k, self._ab, self._ldab,
+                                          self._b, self._ldb, ctypes.byref(self._plan))
+        if rc != 0:
+            _raise(rc, "bandchol_batch_create")
+
+    def factor(self, d_info):
+        """Factor every system in place; info per system into the int64 GPU tensor ``d_info``."""
+        import torch
+        if d_info.dtype != torch.int64 or not d_info.is_cuda or d_info.numel() < self.batch:
+            raise TypeError("d_info must be an int64 GPU tensor with one entry per system")
+        rc = load().bandchol_batch_factor(self._plan, d_info.data_ptr(), _stream())
+        if rc != 0:
+            _raise(rc, "bandchol_batch_factor")
+
+    def solve(self, nrhs):
+        """Overwrite every b with the solution (after ``factor``)."""
+        rc = load().bandchol_batch_solve(self._plan, int(nrhs), _stream())
+        if rc != 0:
+            _raise(rc, "bandchol_batch_solve")
+
+    def close(self):
+        if self._plan:
+            load().bandchol_batch_destroy(self._plan)
+            self._plan = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def finalize():

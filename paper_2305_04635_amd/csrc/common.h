@@ -52,6 +52,16 @@ __device__ __forceinline__ double recip(double d) {
 __device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 typedef __attribute__((address_space(1))) double glb_d;
+typedef __attribute__((address_space(1))) int glb_i;
+
+// Relaxed agent-scope atomic accesses: coherent across the chip's L2 caches
+// without cache maintenance; used for data that other workgroups read.
+__device__ __forceinline__ double aload(const glb_d* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void astore(glb_d* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 struct Band {
   glb_d* ab;
@@ -64,19 +74,47 @@ struct Band {
   __device__ __forceinline__ double ld(int64_t i, int64_t j) const { return in_band(i, j) ? *at(i, j) : 0.0; }
 };
 
+// A lane's run of band elements A(i, j0 + cs*q), q = 0, 1, ...: the first at p,
+// the next ones cs*(ldab-1) doubles apart (A(i, j) sits at ab + i + j*(ldab-1)).
+// Element q is in the band iff i < n and 0 <= d0 - cs*q <= k.  Set up once per
+// tile so that each element costs one compare and one pointer step.
+struct Run {
+  glb_d* p;
+  int64_t step;
+  int d0, ds, k;
+  bool row_ok;
+  __device__ __forceinline__ bool in(int q) const {
+    const int d = d0 - ds * q;
+    return row_ok && d >= 0 && d <= k;
+  }
+  __device__ __forceinline__ glb_d* at(int q) const { return p + step * q; }
+  __device__ __forceinline__ double ld(int q) const { return in(q) ? *at(q) : 0.0; }
+  __device__ __forceinline__ double ald(int q) const { return in(q) ? aload(at(q)) : 0.0; }
+};
+
+__device__ __forceinline__ Run band_run(const Band& a, int64_t i, int64_t j0, int cs) {
+  Run r;
+  r.p = a.ab + i + j0 * (a.ldab - 1);
+  r.step = (int64_t)cs * (a.ldab - 1);
+  r.d0 = (int)(i - j0);
+  r.ds = cs;
+  r.k = (int)(a.k < 0x7fffffff ? a.k : 0x7fffffff);
+  r.row_ok = i < a.n;
+  return r;
+}
+
 // ---------------------------------------------------------------- tile blocks in global memory
 
 // Block (bi, bj) of tile (R, C) into accumulator form.  On a diagonal tile the
 // positions past row n-1 get an identity so that the factorization there is trivial.
 __device__ __forceinline__ d4 blk_load(const Band& a, int64_t R, int64_t C, int bi, int bj) {
   const int lane = lane_id();
-  const int64_t i = R * T + 16 * bi + (lane & 15);
+  const Run run = band_run(a, R * T + 16 * bi + (lane & 15), C * T + 16 * bj + (lane >> 4), 4);
   d4 acc;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const int64_t j = C * T + 16 * bj + 4 * r + (lane >> 4);
-    double v = a.ld(i, j);
-    if (R == C && i == j && i >= a.n) v = 1.0;
+    double v = run.ld(r);
+    if (R == C && !run.row_ok && run.d0 - 4 * r == 0) v = 1.0;
     acc[r] = v;
   }
   return acc;
@@ -84,12 +122,10 @@ __device__ __forceinline__ d4 blk_load(const Band& a, int64_t R, int64_t C, int 
 
 __device__ __forceinline__ void blk_store(const Band& a, int64_t R, int64_t C, int bi, int bj, d4 v) {
   const int lane = lane_id();
-  const int64_t i = R * T + 16 * bi + (lane & 15);
+  const Run run = band_run(a, R * T + 16 * bi + (lane & 15), C * T + 16 * bj + (lane >> 4), 4);
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int64_t j = C * T + 16 * bj + 4 * r + (lane >> 4);
-    if (a.in_band(i, j) && (R != C || j <= i)) *a.at(i, j) = v[r];
-  }
+  for (int r = 0; r < 4; ++r)
+    if (run.in(r)) *run.at(r) = v[r];
 }
 
 // ---------------------------------------------------------------- tiles staged in LDS (column-major, pitch LP)

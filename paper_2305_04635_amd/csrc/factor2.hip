@@ -31,7 +31,6 @@ constexpr int NT = 256;
 // far above any legitimate wait, which lasts a few spine steps.
 constexpr long long SPIN_LIMIT = 1LL << 22;
 
-typedef __attribute__((address_space(1))) int glb_i;
 
 struct Ws {
   glb_i* tflag;     // NB*(K+1): tile (R, R-d) published, index R*(K+1)+d
@@ -50,44 +49,10 @@ struct Args {
   Ws w;
 };
 
-__device__ __forceinline__ double aload(const glb_d* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void astore(glb_d* p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 __device__ __forceinline__ int aflag(const glb_i* p) {
   return __builtin_amdgcn_readfirstlane(__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
 }
 __device__ __forceinline__ void raise_flag(glb_i* p) { __hip_atomic_store(p, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
-
-// A lane's run of band elements A(i, j0 + cs*q), q = 0, 1, ...: the first at p,
-// the next ones cs*(ldab-1) doubles apart (A(i, j) sits at ab + i + j*(ldab-1)).
-// Element q is in the band iff i < n and 0 <= d0 - cs*q <= k.  Set up once per
-// tile so that each element costs one compare and one pointer step.
-struct Run {
-  glb_d* p;
-  int64_t step;
-  int d0, ds, k;
-  bool row_ok;
-  __device__ __forceinline__ bool in(int q) const {
-    const int d = d0 - ds * q;
-    return row_ok && d >= 0 && d <= k;
-  }
-  __device__ __forceinline__ glb_d* at(int q) const { return p + step * q; }
-  __device__ __forceinline__ double ld(int q) const { return in(q) ? aload(at(q)) : 0.0; }
-};
-
-__device__ __forceinline__ Run band_run(const Band& a, int64_t i, int64_t j0, int cs) {
-  Run r;
-  r.p = a.ab + i + j0 * (a.ldab - 1);
-  r.step = (int64_t)cs * (a.ldab - 1);
-  r.d0 = (int)(i - j0);
-  r.ds = cs;
-  r.k = (int)(a.k < 0x7fffffff ? a.k : 0x7fffffff);
-  r.row_ok = i < a.n;
-  return r;
-}
 
 // This wave waits for *f (bounded); every lane gets the same answer.
 __device__ __forceinline__ bool wave_wait(const glb_i* f, const Ws& w) {
@@ -117,7 +82,7 @@ __device__ __forceinline__ d4 ablk_load(const Band& a, int64_t R, int64_t C, int
   d4 acc;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    double v = run.ld(r);
+    double v = run.ald(r);
     if (R == C && !run.row_ok && run.d0 - 4 * r == 0) v = 1.0;
     acc[r] = v;
   }
@@ -155,8 +120,8 @@ __device__ __forceinline__ d4 aterm(const Band& a, int64_t Rx, int64_t Ry, int64
   double xf[T / 4], yf[T / 4];
 #pragma unroll
   for (int q = 0; q < T / 4; ++q) {
-    xf[q] = x.ld(q);
-    yf[q] = y.ld(q);
+    xf[q] = x.ald(q);
+    yf[q] = y.ald(q);
   }
 #pragma unroll
   for (int q = 0; q < T / 4; ++q) acc = mfma_xyt(-xf[q], yf[q], acc);
@@ -360,8 +325,8 @@ __device__ __attribute__((noinline)) void spine_prepare(const Args& A_, int64_t 
     const Run r1 = band_run(A.a, m * T + 16 + (lane & 15), j0, 4);
 #pragma unroll
     for (int q = 0; q < T / 4; ++q) {
-      x0[q] = r0.ld(q);
-      x1[q] = r1.ld(q);
+      x0[q] = r0.ald(q);
+      x1[q] = r1.ald(q);
     }
   }
 #pragma unroll

@@ -1,0 +1,435 @@
+// Single-workgroup band Cholesky ("walk") for narrow bands, and the batched
+// factor and solve built on it (gfx950, FP64).
+//
+// One workgroup factors one matrix, right-looking and in place, with no
+// communication outside the workgroup (Algorithm 1's potrf / trsm / syrk+gemm
+// steps on T x T tiles, Section 3).  Per tile column C:
+//   phase A  wave 0: sweep of the staged diagonal tile -> L(C,C), L(C,C)^{-T};
+//            waves 1-3: the work of column C-1 that the next diagonal tile does
+//            not wait for: trsm of tiles (C-1+d, C-1), d >= 2, then the updates
+//            tile(C-1+dr, C-1+dc) -= L(C-1+dr, C-1) L(C-1+dc, C-1)^T, all pairs but (1,1);
+//   phase B  all waves: trsm of tile (C+1, C) (the critical one);
+//   phase C  waves 1-3: diag = tile(C+1, C+1) - L(C+1, C) L(C+1, C)^T, staged
+//            for the next sweep; wave 0 stores L(C,C)^{-T} when asked to.
+// The current tile column's L tiles stay in LDS (pnl) for the updates.
+//
+// The batched kernels take a descriptor per system and an order (longest
+// first); every workgroup takes the next system from an atomic counter.
+#include <stdint.h>
+
+#include <mutex>
+#include <vector>
+
+#include "common.h"
+#include "walk.h"
+
+namespace bandchol_walk {
+
+using namespace bandchol;
+
+constexpr int NT = 256;
+
+// ----------------------------------------------------------------- tile helpers
+
+// Fragments of row-block bi of tile (R, C): x[q] = A(R*T + 16 bi + l%16, C*T + 4q + l/16).
+__device__ __forceinline__ void rowblk_load(const Band& a, int64_t R, int64_t C, int bi, double (&x)[T / 4]) {
+  const int lane = lane_id();
+  const Run run = band_run(a, R * T + 16 * bi + (lane & 15), C * T + (lane >> 4), 4);
+#pragma unroll
+  for (int q = 0; q < T / 4; ++q) x[q] = run.ld(q);
+}
+
+// out block (bi, bj) = X_rowblk * L^{-T}(:, 16bj..16bj+15); L^{-T} row-major in LDS
+// (pitch LP), upper triangular.
+__device__ __forceinline__ d4 blk_trsm_frag(const double (&x)[T / 4], const lds_d* linvt, int bj) {
+  const int lane = lane_id();
+  const int qmax = 4 * bj + 4;
+  d4 out = {0, 0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < T / 4; ++q)
+    if (q < qmax) out = mfma_xyt(x[q], linvt[(4 * q + (lane >> 4)) * LP + 16 * bj + (lane & 15)], out);
+  return out;
+}
+
+// One wave: tile (R, C) <- tile (R, C) * L(C,C)^{-T}, written to global and to an
+// LDS copy.  Every output block needs the input row-block over all columns, so
+// all input fragments are read before any output is written.
+__device__ __forceinline__ void tile_trsm_wave(const Band& a, int64_t R, int64_t C, const lds_d* linvt, lds_d* lds_out) {
+  double x0[T / 4], x1[T / 4];
+  rowblk_load(a, R, C, 0, x0);
+  rowblk_load(a, R, C, 1, x1);
+  const d4 o00 = blk_trsm_frag(x0, linvt, 0), o01 = blk_trsm_frag(x0, linvt, 1);
+  const d4 o10 = blk_trsm_frag(x1, linvt, 0), o11 = blk_trsm_frag(x1, linvt, 1);
+  blk_to_lds(lds_out, 0, 0, o00); blk_to_lds(lds_out, 0, 1, o01);
+  blk_to_lds(lds_out, 1, 0, o10); blk_to_lds(lds_out, 1, 1, o11);
+  blk_store(a, R, C, 0, 0, o00); blk_store(a, R, C, 0, 1, o01);
+  blk_store(a, R, C, 1, 0, o10); blk_store(a, R, C, 1, 1, o11);
+}
+
+struct WalkLds {
+  lds_d* diag;    // T*LP
+  lds_d* linvt;   // 2 x T*LP (row-major, pitch LP), alternating by column parity
+  lds_d* pnl;     // K x T*LP
+};
+
+__device__ __forceinline__ WalkLds walk_lds(lds_d* base, int K) {
+  WalkLds L;
+  L.diag = base;
+  L.linvt = L.diag + T * LP;
+  L.pnl = L.linvt + 2 * T * LP;
+  (void)K;
+  return L;
+}
+
+// ----------------------------------------------------------------- the walk
+//
+// The noinline functions copy their structure arguments into locals first:
+// the references point at a stack copy, and after every store the fields
+// would otherwise be re-read from memory.
+
+// wave 0: factor the staged diagonal tile, store L(C,C), keep L(C,C)^{-T} in LDS
+__device__ __attribute__((noinline)) void walk_sweep(const Band& a_, int64_t C, const WalkLds& L_, lds_d* lt,
+                                                     lds_i* s_fail) {
+  const Band a = a_;
+  const WalkLds L = L_;
+  const int lane = lane_id();
+  double row[T];
+#pragma unroll
+  for (int c = 0; c < T; ++c) row[c] = lane < T ? L.diag[c * LP + lane] : ((lane - T) == c ? 1.0 : 0.0);
+  const int fail = sweep_ldlt(row, nullptr);
+  if (fail >= 0) {
+    if (lane == 0) *s_fail = fail;
+    return;
+  }
+  const Run run = band_run(a, C * T + (lane & 31), C * T, 1);
+#pragma unroll
+  for (int c = 0; c < T; ++c) {
+    if (lane < T) {
+      if (run.in(c)) *run.at(c) = row[c];
+    } else {
+      lt[(lane - T) * LP + c] = row[c];
+    }
+  }
+}
+
+// waves 1-3: the rest of tile column Cp (trsm of d >= 2, then all updates but the critical one)
+__device__ __attribute__((noinline)) void walk_column_rest(const Band& a_, int K, int64_t NB, int64_t Cp,
+                                                           const WalkLds& L_, const lds_d* lt_prev, lds_i* s_sync,
+                                                           int sync_target) {
+  const Band a = a_;
+  const WalkLds L = L_;
+  const int wave = wave_id(), lane = lane_id();
+  for (int d = 2; d <= K && Cp + d < NB; ++d)
+    if ((d - 2) % 3 == wave - 1) tile_trsm_wave(a, Cp + d, Cp, lt_prev, L.pnl + (size_t)(d - 1) * T * LP);
+  int idx = 0;
+  // waves 1-3 meet before using each other's panel tiles
+  __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): this wave's LDS writes are done
+  if (lane == 0) __hip_atomic_fetch_add(s_sync, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+  while (__hip_atomic_load(s_sync, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < sync_target)
+    __builtin_amdgcn_s_sleep(1);
+  for (int dr = 1; dr <= K && Cp + dr < NB; ++dr) {
+    for (int dc = 1; dc <= dr; ++dc) {
+      if (dr == 1 && dc == 1) continue;
+      for (int blk = 0; blk < 4; ++blk) {
+        const int bi = blk & 1, bj = blk >> 1;
+        if (dr == dc && bj > bi) continue;
+        if (idx++ % 3 != wave - 1) continue;
+        d4 acc = blk_load(a, Cp + dr, Cp + dc, bi, bj);
+        acc = blk_gemm_lds(L.pnl + (size_t)(dr - 1) * T * LP, L.pnl + (size_t)(dc - 1) * T * LP, bi, bj, acc);
+        blk_store(a, Cp + dr, Cp + dc, bi, bj, acc);
+      }
+    }
+  }
+}
+
+// wave 0: L(C,C)^{-T} from LDS (pitch LP) to dense row-major T x T global memory
+__device__ __forceinline__ void store_linvt(const lds_d* lt, double* dst) {
+  const int lane = lane_id();
+  double v[T / 2];
+#pragma unroll
+  for (int p = 0; p < T / 2; ++p) {
+    const int e = 64 * p + lane;
+    v[p] = lt[(e / T) * LP + (e % T)];
+  }
+#pragma unroll
+  for (int p = 0; p < T / 2; ++p) dst[64 * p + lane] = v[p];
+}
+
+// Returns info (0 or the 1-based failing column).  linv: if not null, receives
+// L(C,C)^{-T} (row-major T x T) for every tile column C.
+__device__ int64_t walk_factor(const Band a, const int K, const WalkLds L, double* linv, lds_i* s_fail,
+                               lds_i* s_sync) {
+  const int wave = wave_id();
+  const int64_t NB = (a.n + T - 1) / T;
+  if (threadIdx.x == 0) { *s_fail = -1; *s_sync = 0; }
+  // stage tile (0, 0)
+  if (wave >= 1) {
+    const int bi = (wave >= 2), bj = (wave == 3);
+    blk_to_lds(L.diag, bi, bj, blk_load(a, 0, 0, bi, bj));
+  } else {
+    blk_to_lds(L.diag, 0, 1, d4{0, 0, 0, 0});
+  }
+  __syncthreads();
+  int sync_target = 0;
+  for (int64_t C = 0; C < NB; ++C) {
+    lds_d* lt = L.linvt + (C & 1) * T * LP;
+    const lds_d* lt_prev = L.linvt + ((C + 1) & 1) * T * LP;
+    // ---------------- phase A
+    if (wave == 0) walk_sweep(a, C, L, lt, s_fail);
+    else if (C >= 1) walk_column_rest(a, K, NB, C - 1, L, lt_prev, s_sync, sync_target += 3);
+    wait_vmem();
+    __syncthreads();
+    if (*s_fail >= 0) return C * T + *s_fail + 1;
+    if (C + 1 >= NB) {
+      if (linv && wave == 0) store_linvt(lt, linv + C * T * T);
+      break;
+    }
+    // ---------------- phase B: trsm of tile (C+1, C)
+    if (K >= 1) {
+      const int bi = wave & 1, bj = wave >> 1;
+      double x[T / 4];
+      rowblk_load(a, C + 1, C, bi, x);
+      wait_vmem();
+      __syncthreads();   // every wave holds its input before any output is written
+      const d4 out = blk_trsm_frag(x, lt, bj);
+      blk_to_lds(L.pnl, bi, bj, out);
+      blk_store(a, C + 1, C, bi, bj, out);
+    }
+    wait_vmem();
+    __syncthreads();
+    // ---------------- phase C: stage tile (C+1, C+1) minus the critical update
+    if (wave >= 1) {
+      const int bi = (wave >= 2), bj = (wave == 3);
+      d4 acc = blk_load(a, C + 1, C + 1, bi, bj);
+      if (K >= 1) acc = blk_gemm_lds(L.pnl, L.pnl, bi, bj, acc);
+      blk_to_lds(L.diag, bi, bj, acc);
+    } else {
+      blk_to_lds(L.diag, 0, 1, d4{0, 0, 0, 0});
+      if (linv) store_linvt(lt, linv + C * T * T);
+    }
+    __syncthreads();
+  }
+  return 0;
+}
+
+__global__ void __launch_bounds__(NT) walk_single_kernel(WalkSys w, int K, int64_t* info) {
+  extern __shared__ double lds_dyn[];
+  __shared__ int s_fail, s_sync;
+  const Band a{(glb_d*)w.ab, w.n, w.k, w.ldab};
+  const int64_t res = walk_factor(a, K, walk_lds((lds_d*)lds_dyn, K), w.linv, (lds_i*)&s_fail, (lds_i*)&s_sync);
+  if (threadIdx.x == 0) *info = res;
+}
+
+// Batched factor: systems sys[order[t]] for t = 0, 1, ... taken from *queue.
+__global__ void __launch_bounds__(NT) walk_batch_kernel(const WalkSys* sys, const int* order, int nsys, int Kmax,
+                                                        unsigned* queue, int64_t* info) {
+  extern __shared__ double lds_dyn[];
+  __shared__ int s_idx, s_fail, s_sync;
+  for (;;) {
+    if (threadIdx.x == 0) s_idx = (int)atomicAdd(queue, 1u);
+    __syncthreads();
+    const int t = s_idx;
+    if (t >= nsys) break;
+    const int id = order[t];
+    const WalkSys w = sys[id];
+    const int64_t kk = w.k < w.n - 1 ? w.k : (w.n > 0 ? w.n - 1 : 0);
+    const int K = (int)((kk + T - 1) / T);
+    const Band a{(glb_d*)w.ab, w.n, kk, w.ldab};
+    int64_t res = 0;
+    if (w.n > 0 && K <= Kmax) res = walk_factor(a, K, walk_lds((lds_d*)lds_dyn, Kmax), w.linv, (lds_i*)&s_fail,
+                                                 (lds_i*)&s_sync);
+    if (threadIdx.x == 0) info[id] = res;
+    __syncthreads();
+  }
+}
+
+// ----------------------------------------------------------------- batched solves
+//
+// One workgroup solves one system, block of T rows by block, with up to
+// RHS_PASS right-hand sides per pass; the diagonal blocks are applied through
+// the inverses L(C,C)^{-T} kept by the factorization, so no block waits on a
+// triangular recurrence.  Lane l of every wave owns row (or column) l % 32 and
+// the right-hand sides (l / 32) * (RHS_PASS / 2) ... + RHS_PASS / 2 - 1.  The
+// last K+1 solution blocks stay in an LDS ring.
+//   forward (L Y = B):   s = b_R - sum_{d=1..K} L(R, R-d) y_{R-d};  y_R = L_RR^{-1} s
+//   back   (L^T X = Y):  s = y_C - sum_{d=1..K} L(C+d, C)^T x_{C+d}; x_C = L_CC^{-T} s
+// Waves split the K off-diagonal tiles; their partial sums meet in LDS.
+
+constexpr int RH = RHS_PASS / 2;   // right-hand sides per lane
+
+__device__ __forceinline__ lds_d* ring_at(lds_d* ring, int64_t blk, int K) {
+  return ring + (size_t)(blk % (K + 1)) * T * RHS_PASS;   // [row][rhs]
+}
+
+template <bool FWD>
+__device__ void solve_one(const Band& a, int K, const double* linv, double* b, int64_t ldb, int r0, int nr,
+                          lds_d* ring, lds_d* part) {
+  const int wave = wave_id(), lane = lane_id();
+  const int i = lane & 31, h = lane >> 5;
+  const int64_t NB = (a.n + T - 1) / T;
+  for (int64_t it = 0; it < NB; ++it) {
+    const int64_t R = FWD ? it : NB - 1 - it;
+    double acc[RH];
+#pragma unroll
+    for (int t = 0; t < RH; ++t) acc[t] = 0.0;
+    for (int d = wave + 1; d <= K; d += 4) {
+      const int64_t S = FWD ? R - d : R + d;   // block of the known solution
+      if (S < 0 || S >= NB) continue;
+      const lds_d* ys = ring_at(ring, S, K);
+      if (FWD) {
+        // row i of tile (R, S): A(R*T + i, S*T + j), j = 0..T-1
+        const Run run = band_run(a, R * T + i, S * T, 1);
+#pragma unroll 8
+        for (int j = 0; j < T; ++j) {
+          const double l = run.ld(j);
+#pragma unroll
+          for (int t = 0; t < RH; ++t) acc[t] = fma(l, ys[j * RHS_PASS + h * RH + t], acc[t]);
+        }
+      } else {
+        // column i of tile (S, R): A(S*T + j, R*T + i), j = 0..T-1 (consecutive in memory)
+        const int64_t gi = R * T + i;
+        const int64_t d0 = S * T - gi;   // row offset of j = 0 inside the band column
+        const glb_d* col = a.ab + d0 + gi * a.ldab;
+#pragma unroll 8
+        for (int j = 0; j < T; ++j) {
+          const int64_t dj = d0 + j;
+          const double l = (S * T + j < a.n && dj <= a.k) ? col[j] : 0.0;
+#pragma unroll
+          for (int t = 0; t < RH; ++t) acc[t] = fma(l, ys[j * RHS_PASS + h * RH + t], acc[t]);
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < RH; ++t) part[(wave * T + i) * RHS_PASS + h * RH + t] = acc[t];
+    __syncthreads();
+    if (wave == 0) {
+      // s = b_R - sum of the partials (row i, this lane's right-hand sides)
+      const int64_t gi = R * T + i;
+      double s[RH];
+#pragma unroll
+      for (int t = 0; t < RH; ++t) {
+        const int r = h * RH + t;
+        double v = (gi < a.n && r < nr) ? b[(r0 + r) * ldb + gi] : 0.0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) v -= part[(w * T + i) * RHS_PASS + r];
+        s[t] = v;
+      }
+      lds_d* sbuf = part;   // reuse: [row][rhs]
+      __builtin_amdgcn_s_waitcnt(0xC07F);
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int t = 0; t < RH; ++t) sbuf[i * RHS_PASS + h * RH + t] = s[t];
+      __builtin_amdgcn_s_waitcnt(0xC07F);
+      __builtin_amdgcn_wave_barrier();
+      // y_i = sum_c Linv(i, c) s_c = sum_c linvt[c][i] s_c;  x_i = sum_c Linv(c, i) s_c = sum_c linvt[i][c] s_c
+      const double* lt = linv + R * T * T;
+      double y[RH];
+#pragma unroll
+      for (int t = 0; t < RH; ++t) y[t] = 0.0;
+#pragma unroll 8
+      for (int c = 0; c < T; ++c) {
+        const double l = FWD ? lt[c * T + i] : lt[i * T + c];
+#pragma unroll
+        for (int t = 0; t < RH; ++t) y[t] = fma(l, sbuf[c * RHS_PASS + h * RH + t], y[t]);
+      }
+      lds_d* yr = ring_at(ring, R, K);
+#pragma unroll
+      for (int t = 0; t < RH; ++t) {
+        const int r = h * RH + t;
+        yr[i * RHS_PASS + r] = (gi < a.n) ? y[t] : 0.0;
+        if (gi < a.n && r < nr) b[(r0 + r) * ldb + gi] = y[t];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <bool FWD>
+__global__ void __launch_bounds__(NT) solve_batch_kernel(const WalkSys* sys, const int* order, int nsys, int Kmax,
+                                                         int nrhs, unsigned* queue) {
+  extern __shared__ double lds_dyn[];
+  __shared__ int s_idx;
+  lds_d* part = (lds_d*)lds_dyn;                     // 4 x T x RHS_PASS
+  lds_d* ring = part + 4 * T * RHS_PASS;            // (Kmax+1) x T x RHS_PASS
+  for (;;) {
+    if (threadIdx.x == 0) s_idx = (int)atomicAdd(queue, 1u);
+    __syncthreads();
+    const int t = s_idx;
+    if (t >= nsys) break;
+    const int id = order[t];
+    const WalkSys w = sys[id];
+    const int64_t kk = w.k < w.n - 1 ? w.k : (w.n > 0 ? w.n - 1 : 0);
+    const int K = (int)((kk + T - 1) / T);
+    const Band a{(glb_d*)w.ab, w.n, kk, w.ldab};
+    if (w.n > 0 && K <= Kmax && w.b && w.linv) {
+      for (int r0 = 0; r0 < nrhs; r0 += RHS_PASS) {
+        const int nr = nrhs - r0 < RHS_PASS ? nrhs - r0 : RHS_PASS;
+        solve_one<FWD>(a, K, w.linv, w.b, w.ldb, r0, nr, ring, part);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void batch_clear_kernel(unsigned* queue, int count) {
+  if (threadIdx.x < count) queue[threadIdx.x] = 0;
+}
+
+}  // namespace bandchol_walk
+
+// ----------------------------------------------------------------- host-side launchers
+
+using namespace bandchol_walk;
+
+size_t bandchol_walk_lds_bytes(int K) { return sizeof(double) * ((size_t)T * LP + 2 * T * LP + (size_t)K * T * LP); }
+
+size_t bandchol_solve_batch_lds_bytes(int Kmax) {
+  return sizeof(double) * ((size_t)4 * T * RHS_PASS + (size_t)(Kmax + 1) * T * RHS_PASS);
+}
+
+// Raises a kernel's dynamic LDS limit once to the most any launch can ask for
+// (so that launches under stream capture change no attributes).
+static hipError_t set_lds_attr(const void* fn, size_t lds) {
+  (void)lds;
+  static std::mutex mu;
+  static std::vector<const void*> done;
+  std::lock_guard<std::mutex> lk(mu);
+  for (const void* f : done)
+    if (f == fn) return hipSuccess;
+  const size_t most = bandchol_walk_lds_bytes(WALK_KMAX) > bandchol_solve_batch_lds_bytes(WALK_KMAX)
+                          ? bandchol_walk_lds_bytes(WALK_KMAX)
+                          : bandchol_solve_batch_lds_bytes(WALK_KMAX);
+  const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)most);
+  if (e == hipSuccess) done.push_back(fn);
+  return e;
+}
+
+hipError_t bandchol_walk_single_launch(const WalkSys& w, int K, int64_t* d_info, hipStream_t st) {
+  const size_t lds = bandchol_walk_lds_bytes(K);
+  hipError_t e = set_lds_attr((const void*)walk_single_kernel, lds);
+  if (e != hipSuccess) return e;
+  walk_single_kernel<<<1, NT, lds, st>>>(w, K, d_info);
+  return hipGetLastError();
+}
+
+hipError_t bandchol_walk_batch_factor_launch(const WalkSys* d_sys, const int* d_order, int nsys, int Kmax,
+                                             unsigned* d_queue, int64_t* d_info, int grid, hipStream_t st) {
+  const size_t lds = bandchol_walk_lds_bytes(Kmax);
+  hipError_t e = set_lds_attr((const void*)walk_batch_kernel, lds);
+  if (e != hipSuccess) return e;
+  batch_clear_kernel<<<1, 64, 0, st>>>(d_queue, 1);
+  walk_batch_kernel<<<grid, NT, lds, st>>>(d_sys, d_order, nsys, Kmax, d_queue, d_info);
+  return hipGetLastError();
+}
+
+hipError_t bandchol_walk_batch_solve_launch(const WalkSys* d_sys, const int* d_order, int nsys, int Kmax, int nrhs,
+                                            unsigned* d_queue, int grid, hipStream_t st) {
+  const size_t lds = bandchol_solve_batch_lds_bytes(Kmax);
+  hipError_t e = set_lds_attr((const void*)solve_batch_kernel<true>, lds);
+  if (e == hipSuccess) e = set_lds_attr((const void*)solve_batch_kernel<false>, lds);
+  if (e != hipSuccess) return e;
+  batch_clear_kernel<<<1, 64, 0, st>>>(d_queue, 2);
+  solve_batch_kernel<true><<<grid, NT, lds, st>>>(d_sys, d_order, nsys, Kmax, nrhs, d_queue);
+  solve_batch_kernel<false><<<grid, NT, lds, st>>>(d_sys, d_order, nsys, Kmax, nrhs, d_queue + 1);
+  return hipGetLastError();
+}

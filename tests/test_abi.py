@@ -57,3 +57,30 @@ def test_binding_rejects_cpu_tensors():
     torch = pytest.importorskip("torch")
     with pytest.raises(TypeError):
         bc.factor(torch.zeros(12, dtype=torch.float64), 4, 2)
+
+
+def test_batch_bad_arguments_rejected_on_host():
+    lib = bc.load()
+    I64 = ctypes.c_int64 * 2
+    P = ctypes.c_void_p * 2
+    plan = ctypes.c_void_p()
+    n, k, ldab = I64(10, 20), I64(3, 4), I64(4, 5)
+    ab, b, ldb = P(8, 16), P(24, 32), I64(10, 20)
+    ok = (n, k, ab, ldab, b, ldb)
+
+    def create(batch=2, n=n, k=k, ab=ab, ldab=ldab, b=b, ldb=ldb, plan=ctypes.byref(plan)):
+        return lib.bandchol_batch_create(batch, n, k, ab, ldab, b, ldb, plan)
+
+    assert create(batch=-1) == -1
+    assert create(plan=None) == -8
+    assert create(n=I64(10, -1)) == -2
+    assert create(k=I64(3, -4)) == -3
+    assert create(ab=P(8, None)) == -4
+    assert create(ldab=I64(4, 4)) == -5
+    assert create(b=P(None, 32)) == -6
+    assert create(ldb=I64(10, 19)) == -7
+    assert ok and plan.value is None          # nothing was created
+    assert lib.bandchol_batch_factor(None, 8, None) == -1
+    assert lib.bandchol_batch_solve(None, -1, None) == -1
+    assert lib.bandchol_batch_solve(None, 1, None) == -3
+    lib.bandchol_batch_destroy(None)          # no-op
