@@ -51,6 +51,7 @@ def _load():
             "oracle_band_norm_inf": (ctypes.c_double, [I, I, D, I]),
             "oracle_band_symv": (None, [I, I, D, I, D, D]),
             "oracle_llt_residual_rows": (None, [I, I, D, I, D, I, I, I, D]),
+            "oracle_band_outer_grad": (None, [I, I, I, D, I, D, I, D, I]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -147,6 +148,24 @@ def solve_residual(a_band, k, x, b):
 def opcount(n, k):
     """Operations executed by the factor's loop nest (sqrt = 1 operation)."""
     return int(_load().oracle_pbtrf_opcount(_I64(n), _I64(k)))
+
+
+def band_outer_grad(lam, x, k, n):
+    """Band gradient of sum(w .* x) from x and lambda = A^{-1} w (see band_oracle.c)."""
+    lam = np.asfortranarray(np.asarray(lam, dtype=np.float64).reshape(n, -1))
+    x = np.asfortranarray(np.asarray(x, dtype=np.float64).reshape(n, -1))
+    g = np.zeros((k + 1, n), order="F")
+    _load().oracle_band_outer_grad(n, k, x.shape[1], _p(lam), max(n, 1), _p(x), max(n, 1), _p(g), k + 1)
+    return g
+
+
+def solve_backward(l_band, k, x, w):
+    """Reverse mode of x = A^{-1} b for loss = sum(w .* x) (A = L L^T given by its
+    factor): returns (db, dA_band) with db = A^{-1} w (A is symmetric) and the
+    band gradient of band_outer_grad."""
+    n = l_band.shape[1]
+    lam = solve(l_band, k, np.asarray(w, dtype=np.float64).reshape(n, -1))
+    return lam, band_outer_grad(lam, x, k, n)
 
 
 def cond1_estimate(a_band, l_band, k, itmax=5):

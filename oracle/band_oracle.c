@@ -264,3 +264,30 @@ int64_t oracle_pbtrf_opcount(int64_t n, int64_t k)
     }
     return ops;
 }
+
+/*
+ * Gradient of loss = sum(w .* x), x = A^{-1} b, with respect to the stored
+ * band of the symmetric A, given x and lambda = A^{-1} w (n x nrhs each,
+ * column-major).  The full-matrix gradient is -lambda x^T summed over the
+ * right-hand sides; a stored entry A(i, j), i > j, stands for both A(i, j)
+ * and A(j, i), so its gradient is the sum of the two:
+ *   g(i, j) = -sum_r (lambda(i,r) x(j,r) + lambda(j,r) x(i,r)),  i > j,
+ *   g(i, i) = -sum_r lambda(i,r) x(i,r).
+ * Written to gab in the band layout (ldg >= k+1).
+ */
+void oracle_band_outer_grad(int64_t n, int64_t k, int64_t nrhs, const double *lam, int64_t ldl, const double *x,
+                            int64_t ldx, double *gab, int64_t ldg)
+{
+    for (int64_t j = 0; j < n; ++j) {
+        int64_t dmax = (k < n - 1 - j) ? k : n - 1 - j;
+        for (int64_t d = 0; d <= dmax; ++d) {
+            int64_t i = j + d;
+            double g = 0.0;
+            for (int64_t r = 0; r < nrhs; ++r) {
+                g -= lam[i + r * ldl] * x[j + r * ldx];
+                if (d > 0) g -= lam[j + r * ldl] * x[i + r * ldx];
+            }
+            gab[d + j * ldg] = g;
+        }
+    }
+}
