@@ -17,6 +17,11 @@ factor + solve launches are captured once in a HIP graph; each step replays it
 (bands and right-hand sides restored before each replay, outside the timed
 region).  value = sum_i [n_i(k_i^2+3k_i) + 4 n_i k_i nrhs] / replay time.
 
+--workload adjoint: 64 systems, n = 20000, k = 200 (diagonally dominant), one
+right-hand side each; forward x = A^{-1} b (factor + solve) and the reverse
+mode for loss = sum(w .* x) (db = A^{-1} w and the band gradient of A), all
+captured in one HIP graph; value = forward + backward milliseconds per replay.
+
 Prints ONE JSON line.  N > 1 GPUs is refused: this build runs on one GPU.
 """
 import argparse
@@ -101,7 +106,7 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=10000, help="rows per matrix for the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", action="store_true", help="sampled backward-error check after timing")
-    ap.add_argument("--workload", choices=("sweep", "batched"), default="sweep")
+    ap.add_argument("--workload", choices=("sweep", "batched", "adjoint"), default="sweep")
     ap.add_argument("--batch", type=int, default=512)
     args = ap.parse_args()
 
@@ -118,6 +123,8 @@ def main():
 
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "adjoint":
+        return bench_adjoint(args)
     ks = [int(x) for x in args.ks.split(",")]
     n, nrhs = args.n, args.nrhs
     dev = torch.device("cuda:0")
@@ -349,6 +356,91 @@ def bench_batched(args):
         line["check"] = check
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_batched(ns, ks, nrhs, args.seed)
+    plan.close()
+    print(json.dumps(line))
+
+
+def bench_adjoint(args):
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2305_04635_amd as bc
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    bc.load()
+    bsz, n, k, nrhs = 64, 20000, 200, 1
+    t_gen = time.perf_counter()
+    ab0, b0, w0 = [], [], []
+    for i in range(bsz):
+        ab0.append(torch.from_numpy(synth.band_diagdom(n, k, args.seed + i).ravel(order="F")).to(dev))
+        b0.append(torch.from_numpy(synth.rhs(n, nrhs, args.seed + i).ravel(order="F")).to(dev))
+        w0.append(torch.from_numpy(synth.normal(n * nrhs, args.seed + i, 1)).to(dev))
+    t_gen = time.perf_counter() - t_gen
+    abs_d = [torch.empty_like(t) for t in ab0]
+    bs_d = [torch.empty_like(t) for t in b0]
+    gs_d = [torch.empty_like(t) for t in w0]
+    gabs_d = [torch.zeros_like(t) for t in ab0]
+    plan = bc.BatchPlan([n] * bsz, [k] * bsz, abs_d, bs_d)
+    plan.set_adjoint(gs_d, gabs_d)
+    info = torch.zeros(bsz, dtype=torch.int64, device=dev)
+
+    def restore():
+        torch._foreach_copy_(abs_d, ab0)
+        torch._foreach_copy_(bs_d, b0)
+        torch._foreach_copy_(gs_d, w0)
+
+    def run():
+        plan.factor(info)
+        plan.solve(nrhs)
+        plan.backward(nrhs)
+
+    restore()
+    run()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        run()
+    times = []
+    for s in range(args.warmup + args.steps):
+        restore()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        if s >= args.warmup:
+            times.append(e0.elapsed_time(e1))
+    if any(int(x) != 0 for x in info.cpu().tolist()):
+        print("bench.py: adjoint workload: factorization failed", file=sys.stderr)
+        sys.exit(1)
+    check = None
+    if args.check:
+        import oracle
+        ab = synth.band_diagdom(n, k, args.seed)
+        b = synth.rhs(n, nrhs, args.seed).reshape(n, nrhs)
+        w = synth.normal(n * nrhs, args.seed, 1).reshape(n, nrhs, order="F")
+        l_or, _ = oracle.factor(ab, k)
+        x_or = oracle.solve(l_or, k, b)
+        db_or, gab_or = oracle.solve_backward(l_or, k, x_or, w)
+        db = gs_d[0].cpu().numpy().reshape(n, nrhs, order="F")
+        gab = gabs_d[0].cpu().numpy().reshape(k + 1, n, order="F")
+        check = {"system0_db_rel_err": float(np.linalg.norm(db - db_or) / np.linalg.norm(db_or)),
+                 "system0_dA_rel_err": float(np.linalg.norm(gab - gab_or) / np.linalg.norm(gab_or))}
+    ms = float(np.median(times))
+    line = {
+        "metric": "batched band solve forward+backward time (64 systems, n=20000, k=200, FP64)",
+        "value": round(ms, 4), "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 4), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "x = A^{-1} b and its reverse mode for loss = sum(w .* x), 64 diagonally "
+                               "dominant band systems, one HIP graph replay per step",
+                   "batch": bsz, "n": n, "k": k, "nrhs": nrhs, "replay_ms_min": round(min(times), 4),
+                   "input_generation_s": round(t_gen, 2)},
+    }
+    if check is not None:
+        line["check"] = check
     plan.close()
     print(json.dumps(line))
 

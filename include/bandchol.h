@@ -104,6 +104,26 @@ int64_t bandchol_tile(void);
 int64_t bandchol_set_walk_limit(int64_t kmax);
 
 /*
+ * Reverse mode of the solve, for a loss that depends on x = A^{-1} B through
+ * an upstream gradient G = dloss/dX (n x nrhs): the gradient with respect to B
+ * is A^{-1} G (A is symmetric), computed with two more band solves on the
+ * factor, and the gradient with respect to the stored band of A is
+ * -A^{-1} G X^T folded onto the band, since a stored entry A(i, j), i > j,
+ * stands for both A(i, j) and A(j, i):
+ *   gab(i, j) = -sum_r (lambda(i,r) x(j,r) + lambda(j,r) x(i,r)),  i > j,
+ *   gab(i, i) = -sum_r lambda(i,r) x(i,r),       lambda = A^{-1} G.
+ * (This is the transpose rule of the linear solve; the paper covers only the
+ * forward factorization.)
+ *   n -1, k -2, nrhs -3, ab = factor from bandchol_factor -4, ldab >= k+1 -5,
+ *   x = solution (device, n x nrhs) -6, ldx >= max(1,n) -7,
+ *   g = upstream gradient (device, n x nrhs), overwritten by A^{-1} G -8,
+ *   ldg >= max(1,n) -9, gab = band gradient (device, written) -10,
+ *   ldgab >= k+1 -11.  Stream-ordered on `stream`; no host synchronisation.
+ */
+int64_t bandchol_solve_backward(int64_t n, int64_t k, int64_t nrhs, const double* ab, int64_t ldab, const double* x,
+                                int64_t ldx, double* g, int64_t ldg, double* gab, int64_t ldgab, void* stream);
+
+/*
  * Batches of independent systems of different orders and bandwidths.  The
  * paper's method factors one band at a time; a single band only offers the
  * parallelism of its own tile columns (Section 6 notes how little there is at
@@ -141,6 +161,22 @@ int64_t bandchol_batch_create(int64_t batch, const int64_t* n, const int64_t* k,
                               const int64_t* ldab, double* const* b, const int64_t* ldb, bandchol_batch_t* plan);
 int64_t bandchol_batch_factor(bandchol_batch_t plan, int64_t* d_info, void* stream);
 int64_t bandchol_batch_solve(bandchol_batch_t plan, int64_t nrhs, void* stream);
+/*
+ * Reverse mode for a whole batch (as bandchol_solve_backward per system).
+ * bandchol_batch_set_adjoint registers, per system, the upstream gradient
+ * g[i] (device, n[i] x nrhs, overwritten by A^{-1} G) and the band gradient
+ * gab[i] (device, leading dimension ldgab[i] >= k[i]+1): HOST arrays of
+ * length batch; it allocates and uploads descriptors synchronously (-1 plan
+ * NULL or created without right-hand sides, -2 g, -3 gab, -4 ldgab).
+ * bandchol_batch_backward(nrhs) then only launches kernels on `stream`
+ * (capturable), using the factors and inverses of the last
+ * bandchol_batch_factor and the solutions X left in b by bandchol_batch_solve
+ * (-1 plan NULL or no adjoint buffers, -2 nrhs).
+ */
+int64_t bandchol_batch_set_adjoint(bandchol_batch_t plan, double* const* g, double* const* gab,
+                                   const int64_t* ldgab);
+int64_t bandchol_batch_backward(bandchol_batch_t plan, int64_t nrhs, void* stream);
+
 /* Frees the plan's device memory (waits for the device first). */
 void bandchol_batch_destroy(bandchol_batch_t plan);
 

@@ -35,6 +35,9 @@ SIGNATURES = {
     "bandchol_batch_factor": (_I64, [_VP, _VP, _VP]),
     "bandchol_batch_solve": (_I64, [_VP, _I64, _VP]),
     "bandchol_batch_destroy": (None, [_VP]),
+    "bandchol_solve_backward": (_I64, [_I64, _I64, _I64, _VP, _I64, _VP, _I64, _VP, _I64, _VP, _I64, _VP]),
+    "bandchol_batch_set_adjoint": (_I64, [_VP, _VP, _VP, _VP]),
+    "bandchol_batch_backward": (_I64, [_VP, _I64, _VP]),
 }
 
 EHIP = -1000
@@ -138,6 +141,21 @@ def solve_async(ab, n, k, b, nrhs=None, ldab=None, ldb=None):
         _raise(rc, "bandchol_solve_async")
 
 
+def solve_backward(ab, n, k, x, g, gab, nrhs=None, ldab=None, ldgab=None):
+    """Reverse mode of ``solve`` (stream-ordered): ``g`` (upstream gradient, n x nrhs
+    column-major) becomes A^{-1} G; ``gab`` receives the band gradient of A."""
+    ldab = k + 1 if ldab is None else ldab
+    ldgab = k + 1 if ldgab is None else ldgab
+    for t, name in ((ab, "ab"), (x, "x"), (g, "g"), (gab, "gab")):
+        _check_tensor(t, name)
+    nrhs = (x.numel() // max(n, 1)) if nrhs is None else nrhs
+    ld = max(n, 1)
+    rc = load().bandchol_solve_backward(n, k, nrhs, ab.data_ptr(), ldab, x.data_ptr(), ld, g.data_ptr(), ld,
+                                        gab.data_ptr(), ldgab, _stream())
+    if rc != 0:
+        _raise(rc, "bandchol_solve_backward")
+
+
 class BatchPlan:
     """Batch of independent band systems (``bandchol_batch_*``).
 
@@ -190,6 +208,28 @@ class BatchPlan:
         if rc != 0:
             _raise(rc, "bandchol_batch_solve")
 
+    def set_adjoint(self, gs, gabs, ldgabs=None):
+        """Register per-system upstream gradients (overwritten by A^{-1} G) and band gradients."""
+        if len(gs) != self.batch or len(gabs) != self.batch:
+            raise ValueError("one g and one gab per system")
+        for t in list(gs) + list(gabs):
+            _check_tensor(t, "g/gab")
+        PTR = ctypes.c_void_p * max(self.batch, 1)
+        I64 = ctypes.c_int64 * max(self.batch, 1)
+        self._g = PTR(*[t.data_ptr() for t in gs])
+        self._gab = PTR(*[t.data_ptr() for t in gabs])
+        self._ldgab = I64(*([k + 1 for k in self._k[:self.batch]] if ldgabs is None else ldgabs))
+        self._keep_adj = (list(gs), list(gabs))
+        rc = load().bandchol_batch_set_adjoint(self._plan, self._g, self._gab, self._ldgab)
+        if rc != 0:
+            _raise(rc, "bandchol_batch_set_adjoint")
+
+    def backward(self, nrhs):
+        """Reverse mode for every system (after ``factor``, ``solve`` and ``set_adjoint``)."""
+        rc = load().bandchol_batch_backward(self._plan, int(nrhs), _stream())
+        if rc != 0:
+            _raise(rc, "bandchol_batch_backward")
+
     def close(self):
         if self._plan:
             load().bandchol_batch_destroy(self._plan)
@@ -200,6 +240,95 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+# ----------------------------------------------------------------- autograd
+
+def _autograd_functions():
+    import torch
+
+    class BandSolve(torch.autograd.Function):
+        """x = A^{-1} b with A given by its lower band ``ab`` of shape (n, k+1)
+        (row j = band column j) and b of shape (n,) or (n, nrhs).  Backward:
+        db = A^{-1} dx, dab = band gradient (see bandchol_solve_backward)."""
+
+        @staticmethod
+        def forward(ctx, ab, b, k):
+            n = ab.shape[0]
+            l = ab.detach().contiguous().clone()
+            info = factor(l, n, k)
+            if info != 0:
+                raise BandCholError("matrix is not positive definite (info = %d)" % info)
+            xb = b.detach().t().contiguous() if b.dim() == 2 else b.detach().contiguous().clone()
+            nrhs = b.shape[1] if b.dim() == 2 else 1
+            solve_async(l, n, k, xb, nrhs=nrhs)
+            ctx.k, ctx.nrhs, ctx.two_d = k, nrhs, b.dim() == 2
+            ctx.save_for_backward(l, xb)
+            return xb.t() if b.dim() == 2 else xb
+
+        @staticmethod
+        def backward(ctx, gx):
+            l, xb = ctx.saved_tensors
+            n, k = l.shape[0], ctx.k
+            g = gx.t().contiguous() if ctx.two_d else gx.contiguous().clone()
+            gab = torch.zeros_like(l)
+            solve_backward(l, n, k, xb, g, gab, nrhs=ctx.nrhs)
+            return gab, (g.t() if ctx.two_d else g), None
+
+    class BandSolveBatch(torch.autograd.Function):
+        """Batch of equal-shape systems: ab (B, n, k+1), b (B, n, nrhs) -> x (B, n, nrhs),
+        through one BatchPlan (factor, solve and reverse mode batched)."""
+
+        @staticmethod
+        def forward(ctx, ab, b, k):
+            bsz, n = ab.shape[0], ab.shape[1]
+            nrhs = b.shape[2]
+            l = ab.detach().contiguous().clone()
+            xb = b.detach().transpose(1, 2).contiguous()
+            plan = BatchPlan([n] * bsz, [k] * bsz, [l[i] for i in range(bsz)], [xb[i] for i in range(bsz)])
+            info = torch.zeros(bsz, dtype=torch.int64, device=ab.device)
+            plan.factor(info)
+            plan.solve(nrhs)
+            bad = torch.nonzero(info).flatten().tolist()
+            if bad:
+                plan.close()
+                raise BandCholError("systems %s are not positive definite" % bad)
+            ctx.plan, ctx.nrhs = plan, nrhs
+            ctx.save_for_backward(l, xb)
+            return xb.transpose(1, 2)
+
+        @staticmethod
+        def backward(ctx, gx):
+            l, xb = ctx.saved_tensors
+            g = gx.transpose(1, 2).contiguous()
+            gab = torch.zeros_like(l)
+            plan = ctx.plan
+            plan.set_adjoint([g[i] for i in range(g.shape[0])], [gab[i] for i in range(gab.shape[0])])
+            plan.backward(ctx.nrhs)
+            torch.cuda.current_stream().synchronize()
+            plan.close()
+            return gab, g.transpose(1, 2), None
+
+    return BandSolve, BandSolveBatch
+
+
+_FUNCS = None
+
+
+def band_solve(ab, b, k):
+    """Differentiable x = A^{-1} b (see BandSolve)."""
+    global _FUNCS
+    if _FUNCS is None:
+        _FUNCS = _autograd_functions()
+    return _FUNCS[0].apply(ab, b, k)
+
+
+def band_solve_batch(ab, b, k):
+    """Differentiable batched x = A^{-1} b (see BandSolveBatch)."""
+    global _FUNCS
+    if _FUNCS is None:
+        _FUNCS = _autograd_functions()
+    return _FUNCS[1].apply(ab, b, k)
 
 
 def finalize():

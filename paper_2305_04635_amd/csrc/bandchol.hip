@@ -26,6 +26,7 @@
 
 #include "bandchol.h"
 
+#include "adjoint.h"
 #include "common.h"
 #include "walk.h"
 
@@ -183,6 +184,34 @@ int64_t factor_async_impl(int64_t n, int64_t k, double* ab, int64_t ldab, int64_
 }
 
 int64_t solve_async_impl(int64_t n, int64_t k, int64_t nrhs, const double* ab, int64_t ldab, double* b,
+                         int64_t ldb, hipStream_t st);
+
+int64_t solve_backward_impl(int64_t n, int64_t k, int64_t nrhs, const double* ab, int64_t ldab, const double* x,
+                            int64_t ldx, double* g, int64_t ldg, double* gab, int64_t ldgab, hipStream_t st) {
+  if (n < 0) return -1;
+  if (k < 0) return -2;
+  if (nrhs < 0) return -3;
+  if (ab == nullptr && n > 0) return -4;
+  if (ldab < k + 1) return -5;
+  if (x == nullptr && n > 0 && nrhs > 0) return -6;
+  if (ldx < (n > 1 ? n : 1)) return -7;
+  if (g == nullptr && n > 0 && nrhs > 0) return -8;
+  if (ldg < (n > 1 ? n : 1)) return -9;
+  if (gab == nullptr && n > 0) return -10;
+  if (ldgab < k + 1) return -11;
+  if (n == 0) return 0;
+  const int64_t kk = k < n - 1 ? k : n - 1;
+  if (nrhs > 0) {
+    const int64_t rc = solve_async_impl(n, k, nrhs, ab, ldab, g, ldg, st);
+    if (rc != 0) return rc;
+  }
+  const bandchol_adj::AdjSys w{g, x, gab, n, kk, nrhs, ldg, ldx, ldgab};
+  const hipError_t e = bandchol_outer_grad_launch1(w, st);
+  if (e != hipSuccess) { set_err("solve backward", e); return BANDCHOL_EHIP; }
+  return 0;
+}
+
+int64_t solve_async_impl(int64_t n, int64_t k, int64_t nrhs, const double* ab, int64_t ldab, double* b,
                          int64_t ldb, hipStream_t st) {
   if (n < 0) return -1;
   if (k < 0) return -2;
@@ -225,6 +254,13 @@ struct bandchol_batch {
   int64_t* d_walk_id = nullptr;   // batch index of each walk system (device copy)
   void* d_wide_ws = nullptr;
   int grid = 1;
+  // adjoint buffers (bandchol_batch_set_adjoint)
+  void* adj_mem = nullptr;
+  WalkSys* d_sys_adj = nullptr;                   // walk descriptors with b = g
+  bandchol_adj::AdjSys* d_adj = nullptr;          // every system (walk and wide)
+  std::vector<bandchol_adj::AdjSys> adj;          // host copy, batch order
+  std::vector<double*> wide_g;
+  int64_t nmax = 0;
 };
 
 namespace {
@@ -301,6 +337,12 @@ void bandchol_finalize(void) {
 }
 
 int64_t bandchol_tile(void) { return T; }
+
+int64_t bandchol_solve_backward(int64_t n, int64_t k, int64_t nrhs, const double* ab, int64_t ldab, const double* x,
+                                int64_t ldx, double* g, int64_t ldg, double* gab, int64_t ldgab, void* stream) {
+  g_err[0] = 0;
+  return solve_backward_impl(n, k, nrhs, ab, ldab, x, ldx, g, ldg, gab, ldgab, (hipStream_t)stream);
+}
 
 int64_t bandchol_batch_create(int64_t batch, const int64_t* n, const int64_t* k, double* const* ab,
                               const int64_t* ldab, double* const* b, const int64_t* ldb, bandchol_batch_t* plan) {
@@ -429,6 +471,78 @@ int64_t bandchol_batch_solve(bandchol_batch_t p, int64_t nrhs, void* stream) {
   return 0;
 }
 
+int64_t bandchol_batch_set_adjoint(bandchol_batch_t p, double* const* g, double* const* gab, const int64_t* ldgab) {
+  g_err[0] = 0;
+  if (p == nullptr) return -1;
+  if (!p->has_rhs) return -1;
+  if (p->batch > 0 && g == nullptr) return -2;
+  if (p->batch > 0 && gab == nullptr) return -3;
+  if (p->batch > 0 && ldgab == nullptr) return -4;
+  // batch index -> system
+  std::vector<const WalkSys*> sys(p->batch, nullptr);
+  for (size_t j = 0; j < p->walk.size(); ++j) sys[p->walk_id[j]] = &p->walk[j];
+  for (size_t j = 0; j < p->wide.size(); ++j) sys[p->wide_id[j]] = &p->wide[j];
+  for (int64_t i = 0; i < p->batch; ++i) {
+    if (g[i] == nullptr && sys[i]->n > 0) return -2;
+    if (gab[i] == nullptr && sys[i]->n > 0) return -3;
+    if (ldgab[i] < sys[i]->k + 1) return -4;
+  }
+  std::vector<WalkSys> walk_adj = p->walk;
+  for (size_t j = 0; j < walk_adj.size(); ++j) {
+    walk_adj[j].b = g[p->walk_id[j]];
+    walk_adj[j].ldb = walk_adj[j].n > 1 ? walk_adj[j].n : 1;
+  }
+  p->wide_g.clear();
+  for (size_t j = 0; j < p->wide.size(); ++j) p->wide_g.push_back(g[p->wide_id[j]]);
+  p->adj.clear();
+  p->nmax = 0;
+  for (int64_t i = 0; i < p->batch; ++i) {
+    const WalkSys& w = *sys[i];
+    const int64_t ld = w.n > 1 ? w.n : 1;
+    p->adj.push_back(bandchol_adj::AdjSys{g[i], w.b, gab[i], w.n, w.k, 0, ld, w.ldb, ldgab[i]});
+    p->nmax = std::max(p->nmax, w.n);
+  }
+  const size_t off_adj = align_up(sizeof(WalkSys) * walk_adj.size());
+  const size_t total = off_adj + sizeof(bandchol_adj::AdjSys) * p->adj.size();
+  if (p->adj_mem) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(p->adj_mem);
+    p->adj_mem = nullptr;
+  }
+  hipError_t e = hipMalloc(&p->adj_mem, total > 0 ? total : 256);
+  if (e != hipSuccess) { set_err("adjoint allocation", e); return BANDCHOL_EHIP; }
+  p->d_sys_adj = (WalkSys*)p->adj_mem;
+  p->d_adj = (bandchol_adj::AdjSys*)((char*)p->adj_mem + off_adj);
+  if (!walk_adj.empty())
+    e = hipMemcpy(p->d_sys_adj, walk_adj.data(), sizeof(WalkSys) * walk_adj.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !p->adj.empty())
+    e = hipMemcpy(p->d_adj, p->adj.data(), sizeof(bandchol_adj::AdjSys) * p->adj.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) { set_err("adjoint upload", e); return BANDCHOL_EHIP; }
+  return 0;
+}
+
+int64_t bandchol_batch_backward(bandchol_batch_t p, int64_t nrhs, void* stream) {
+  g_err[0] = 0;
+  if (p == nullptr) return -1;
+  if (nrhs < 0 || nrhs > (int64_t)0x7fffffff) return -2;
+  if (p->adj_mem == nullptr) return -1;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipSuccess;
+  const int nw = (int)p->walk.size();
+  if (nrhs > 0 && nw > 0)
+    e = bandchol_walk_batch_solve_launch(p->d_sys_adj, p->d_order, nw, p->walk_kmax, (int)nrhs, p->d_queue + 8,
+                                         p->grid, st);
+  for (size_t j = 0; j < p->wide.size() && e == hipSuccess && nrhs > 0; ++j) {
+    const WalkSys& w = p->wide[j];
+    if (w.n == 0) continue;
+    e = bandchol_solve_launch(w.n, w.k, nrhs, w.ab, w.ldab, p->wide_g[j], w.n > 1 ? w.n : 1, p->d_wide_ws,
+                              num_cus(), st);
+  }
+  if (e == hipSuccess) e = bandchol_outer_grad_launch(p->d_adj, (int)p->batch, p->nmax, nrhs, st);
+  if (e != hipSuccess) { set_err("batch backward", e); return BANDCHOL_EHIP; }
+  return 0;
+}
+
 void bandchol_batch_destroy(bandchol_batch_t p) {
   if (p == nullptr) return;
   int cur = 0;
@@ -436,6 +550,7 @@ void bandchol_batch_destroy(bandchol_batch_t p) {
   (void)hipSetDevice(p->device);
   (void)hipDeviceSynchronize();
   if (p->mem) (void)hipFree(p->mem);
+  if (p->adj_mem) (void)hipFree(p->adj_mem);
   (void)hipSetDevice(cur);
   delete p;
 }

@@ -143,7 +143,7 @@ __device__ __attribute__((noinline)) void walk_column_rest(const Band& a_, int K
 }
 
 // wave 0: L(C,C)^{-T} from LDS (pitch LP) to dense row-major T x T global memory
-__device__ __forceinline__ void store_linvt(const lds_d* lt, double* dst) {
+__device__ __forceinline__ void store_linvt(const lds_d* lt, glb_d* dst) {
   const int lane = lane_id();
   double v[T / 2];
 #pragma unroll
@@ -181,7 +181,7 @@ __device__ int64_t walk_factor(const Band a, const int K, const WalkLds L, doubl
     __syncthreads();
     if (*s_fail >= 0) return C * T + *s_fail + 1;
     if (C + 1 >= NB) {
-      if (linv && wave == 0) store_linvt(lt, linv + C * T * T);
+      if (linv && wave == 0) store_linvt(lt, (glb_d*)linv + C * T * T);
       break;
     }
     // ---------------- phase B: trsm of tile (C+1, C)
@@ -205,7 +205,7 @@ __device__ int64_t walk_factor(const Band a, const int K, const WalkLds L, doubl
       blk_to_lds(L.diag, bi, bj, acc);
     } else {
       blk_to_lds(L.diag, 0, 1, d4{0, 0, 0, 0});
-      if (linv) store_linvt(lt, linv + C * T * T);
+      if (linv) store_linvt(lt, (glb_d*)linv + C * T * T);
     }
     __syncthreads();
   }
@@ -262,7 +262,7 @@ __device__ __forceinline__ lds_d* ring_at(lds_d* ring, int64_t blk, int K) {
 }
 
 template <bool FWD>
-__device__ void solve_one(const Band& a, int K, const double* linv, double* b, int64_t ldb, int r0, int nr,
+__device__ void solve_one(const Band& a, int K, const glb_d* linv, glb_d* b, int64_t ldb, int r0, int nr,
                           lds_d* ring, lds_d* part) {
   const int wave = wave_id(), lane = lane_id();
   const int i = lane & 31, h = lane >> 5;
@@ -322,7 +322,7 @@ __device__ void solve_one(const Band& a, int K, const double* linv, double* b, i
       __builtin_amdgcn_s_waitcnt(0xC07F);
       __builtin_amdgcn_wave_barrier();
       // y_i = sum_c Linv(i, c) s_c = sum_c linvt[c][i] s_c;  x_i = sum_c Linv(c, i) s_c = sum_c linvt[i][c] s_c
-      const double* lt = linv + R * T * T;
+      const glb_d* lt = linv + R * T * T;
       double y[RH];
 #pragma unroll
       for (int t = 0; t < RH; ++t) y[t] = 0.0;
@@ -364,7 +364,7 @@ __global__ void __launch_bounds__(NT) solve_batch_kernel(const WalkSys* sys, con
     if (w.n > 0 && K <= Kmax && w.b && w.linv) {
       for (int r0 = 0; r0 < nrhs; r0 += RHS_PASS) {
         const int nr = nrhs - r0 < RHS_PASS ? nrhs - r0 : RHS_PASS;
-        solve_one<FWD>(a, K, w.linv, w.b, w.ldb, r0, nr, ring, part);
+        solve_one<FWD>(a, K, (const glb_d*)w.linv, (glb_d*)w.b, w.ldb, r0, nr, ring, part);
       }
     }
     __syncthreads();

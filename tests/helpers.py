@@ -41,3 +41,29 @@ def gpu_solve(l_band, k, b):
 def rel_fro(x, ref):
     den = np.linalg.norm(ref)
     return float(np.linalg.norm(x - ref) / den) if den > 0 else float(np.linalg.norm(x))
+
+
+def dense_of(ab, k):
+    """The symmetric dense matrix whose lower band is ab."""
+    n = ab.shape[1]
+    a = np.zeros((n, n))
+    for j in range(n):
+        for d in range(min(k, n - 1 - j) + 1):
+            a[j + d, j] = ab[d, j]
+            a[j, j + d] = ab[d, j]
+    return a
+
+
+def dense_band_grad(ab, k, b, w):
+    """Gradient of sum(w .* A^{-1} b) with respect to the stored band, from dense
+    numpy solves: -lambda x^T folded onto the band (i > j gets G_ij + G_ji)."""
+    a = dense_of(ab, k)
+    x = np.linalg.solve(a, b)
+    lam = np.linalg.solve(a, w)
+    g = -(lam @ x.T)
+    n = ab.shape[1]
+    out = np.zeros((k + 1, n), order="F")
+    for j in range(n):
+        for d in range(min(k, n - 1 - j) + 1):
+            out[d, j] = g[j + d, j] + (g[j, j + d] if d else 0.0)
+    return out

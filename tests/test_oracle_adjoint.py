@@ -17,36 +17,13 @@ import pytest
 
 import oracle
 import synth
+from helpers import dense_band_grad
 
 
 def loss(ab, k, b, w):
     l, info = oracle.factor(ab, k)
     assert info == 0
     return float(np.sum(w * oracle.solve(l, k, b)))
-
-
-def dense_of(ab, k):
-    n = ab.shape[1]
-    a = np.zeros((n, n))
-    for j in range(n):
-        for d in range(min(k, n - 1 - j) + 1):
-            a[j + d, j] = ab[d, j]
-            a[j, j + d] = ab[d, j]
-    return a
-
-
-def dense_band_grad(ab, k, b, w):
-    """-lambda x^T from dense solves, folded onto the stored band (i > j gets G_ij + G_ji)."""
-    a = dense_of(ab, k)
-    x = np.linalg.solve(a, b)
-    lam = np.linalg.solve(a, w)
-    g = -(lam @ x.T)
-    n = ab.shape[1]
-    out = np.zeros((k + 1, n), order="F")
-    for j in range(n):
-        for d in range(min(k, n - 1 - j) + 1):
-            out[d, j] = g[j + d, j] + (g[j, j + d] if d else 0.0)
-    return out
 
 
 @pytest.mark.parametrize("n,k,nrhs", [(300, 20, 2), (97, 96, 1), (200, 1, 3)])
