@@ -52,6 +52,7 @@ def _load():
             "oracle_band_symv": (None, [I, I, D, I, D, D]),
             "oracle_llt_residual_rows": (None, [I, I, D, I, D, I, I, I, D]),
             "oracle_band_outer_grad": (None, [I, I, I, D, I, D, I, D, I]),
+            "oracle_spbtrf": (ctypes.c_int64, [I, I, ctypes.POINTER(ctypes.c_float), I]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -166,6 +167,58 @@ def solve_backward(l_band, k, x, w):
     n = l_band.shape[1]
     lam = solve(l_band, k, np.asarray(w, dtype=np.float64).reshape(n, -1))
     return lam, band_outer_grad(lam, x, k, n)
+
+
+def spbtrf(ab32, k):
+    """FP32 band Cholesky in place on a float32 (ldab, n) Fortran-order array; returns info."""
+    assert ab32.dtype == np.float32 and ab32.flags.f_contiguous
+    return int(_load().oracle_spbtrf(ab32.shape[1], k, ab32.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                     ab32.shape[0]))
+
+
+def mixed_solve(ab, k, b, itmax=30, ratio=0.5):
+    """Mixed-precision solve of A X = B: FP32 factor of fl32(A), then FP64
+    iterative refinement (residual b - A x in FP64, correction solved with the
+    FP32 factor widened to FP64), as in Buttari et al. (2007) and LAPACK dsposv.
+
+    Stops when every column satisfies ||r||_inf <= sqrt(n) u64 ||A||_inf ||x||_inf.
+    Falls back to the FP64 factor and solve when the FP32 factor fails, after
+    itmax corrections, or when a correction is not at most `ratio` times the
+    previous one.  Returns (x, iterations, fallback) with fallback one of
+    None, "factor", "iterations", "stagnation"."""
+    n = ab.shape[1]
+    b = np.asfortranarray(np.asarray(b, dtype=np.float64).reshape(n, -1))
+    eps = 2.0 ** -53
+    anrm = norm_inf(ab, k)
+    a32 = np.asfortranarray(ab.astype(np.float32))
+    reason = None
+    if spbtrf(a32, k) != 0:
+        reason = "factor"
+    it = 0
+    if reason is None:
+        l = np.asfortranarray(a32.astype(np.float64))
+        x = solve(l, k, b)
+        dprev = None
+        while True:
+            r = b - np.column_stack([symv(ab, k, x[:, c]) for c in range(x.shape[1])])
+            rn = np.max(np.abs(r), axis=0)
+            xn = np.max(np.abs(x), axis=0)
+            if np.all(rn <= np.sqrt(n) * eps * anrm * xn):
+                return x, it, None
+            if it == itmax:
+                reason = "iterations"
+                break
+            d = solve(l, k, r)
+            dn = np.max(np.abs(d), axis=0)
+            if dprev is not None and np.any(dn > ratio * dprev):
+                reason = "stagnation"
+                break
+            x = x + d
+            dprev = dn
+            it += 1
+    l64, info = factor(ab, k)
+    assert info == 0, info
+    return solve(l64, k, b), it, reason
 
 
 def cond1_estimate(a_band, l_band, k, itmax=5):

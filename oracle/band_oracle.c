@@ -291,3 +291,33 @@ void oracle_band_outer_grad(int64_t n, int64_t k, int64_t nrhs, const double *la
         }
     }
 }
+
+/*
+ * FP32 band Cholesky: Algorithm 2 (row by row, inner bound l <= j-1) with
+ * every operation in single precision (float products and sums, sqrtf,
+ * float division), on a float band in the LAPACK lower layout.  Used by the
+ * mixed-precision reference; returns info as oracle_pbtrf.
+ */
+int64_t oracle_spbtrf(int64_t n, int64_t k, float *ab, int64_t ldab)
+{
+    if (n < 0) return -1;
+    if (k < 0) return -2;
+    if (ab == NULL && n > 0) return -3;
+    if (ldab < k + 1) return -4;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t lo = i - k > 0 ? i - k : 0;
+        for (int64_t j = lo; j <= i; ++j) {
+            float t = 0.0f;
+            for (int64_t l = lo; l < j; ++l)
+                t += ab[(i - l) + l * ldab] * ab[(j - l) + l * ldab];
+            if (i == j) {
+                float d = ab[j * ldab] - t;
+                if (!(d > 0.0f)) return i + 1;
+                ab[j * ldab] = sqrtf(d);
+            } else {
+                ab[(i - j) + j * ldab] = (ab[(i - j) + j * ldab] - t) / ab[j * ldab];
+            }
+        }
+    }
+    return 0;
+}
