@@ -22,6 +22,12 @@ right-hand side each; forward x = A^{-1} b (factor + solve) and the reverse
 mode for loss = sum(w .* x) (db = A^{-1} w and the band gradient of A), all
 captured in one HIP graph; value = forward + backward milliseconds per replay.
 
+--workload mixed: n = 1e5, k = 1000, nrhs = 8, A = L0 L0^T + 10^(-2d) ||A|| I with
+L0's diagonal 10^U[-d, 0], d = 1..5; the mixed-precision solve (FP32 factor +
+FP64 refinement, FP64 fallback) against the FP64 factor + solve on the same
+input.  value = mixed-precision milliseconds summed over d (one run per d after
+a warm-up); iterations, fallbacks and errors per d in config.
+
 Prints ONE JSON line.  N > 1 GPUs is refused: this build runs on one GPU.
 """
 import argparse
@@ -106,7 +112,7 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=10000, help="rows per matrix for the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", action="store_true", help="sampled backward-error check after timing")
-    ap.add_argument("--workload", choices=("sweep", "batched", "adjoint"), default="sweep")
+    ap.add_argument("--workload", choices=("sweep", "batched", "adjoint", "mixed"), default="sweep")
     ap.add_argument("--batch", type=int, default=512)
     args = ap.parse_args()
 
@@ -125,6 +131,8 @@ def main():
         return bench_batched(args)
     if args.workload == "adjoint":
         return bench_adjoint(args)
+    if args.workload == "mixed":
+        return bench_mixed(args)
     ks = [int(x) for x in args.ks.split(",")]
     n, nrhs = args.n, args.nrhs
     dev = torch.device("cuda:0")
@@ -442,6 +450,72 @@ def bench_adjoint(args):
     if check is not None:
         line["check"] = check
     plan.close()
+    print(json.dumps(line))
+
+
+def bench_mixed(args):
+    import numpy as np
+    import torch
+
+    import oracle
+    import synth
+    import paper_2305_04635_amd as bc
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    bc.load()
+    n, k, nrhs = args.n, 1000, 8
+    per_d, total_mixed, total_fp64 = [], 0.0, 0.0
+    for d in (1, 2, 3, 4, 5):
+        ab, _ = synth.band_ipm(n, k, args.seed + d, diag_exp_lo=-float(d), shift_rel=10.0 ** (-2 * d))
+        b = synth.rhs(n, nrhs, args.seed + d)
+        dab = torch.from_numpy(ab.ravel(order="F")).to(dev)
+        db = torch.from_numpy(np.asarray(b).ravel(order="F")).to(dev)
+        x = torch.empty_like(db)
+        l = torch.empty_like(dab)
+        x64 = torch.empty_like(db)
+        info = torch.zeros(1, dtype=torch.int64, device=dev)
+        ms_m, ms_64 = [], []
+        for rep_i in range(1 + max(1, args.steps // 5)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            it, fb = bc.mixed_solve(dab, n, k, db, x, nrhs=nrhs)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            l.copy_(dab)
+            x64.copy_(db)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            bc.factor_async(l, n, k, info)
+            bc.solve_async(l, n, k, x64, nrhs=nrhs)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            if rep_i:
+                ms_m.append((t1 - t0) * 1e3)
+                ms_64.append((t3 - t2) * 1e3)
+        xh = x.cpu().numpy().reshape(n, nrhs, order="F")
+        x64h = x64.cpu().numpy().reshape(n, nrhs, order="F")
+        anrm = oracle.norm_inf(ab, k)
+        bwd = max(float(np.max(np.abs(b[:, c] - oracle.symv(ab, k, xh[:, c])))) /
+                  (anrm * float(np.max(np.abs(xh[:, c])))) for c in range(nrhs))
+        fwd = float(np.max(np.abs(xh - x64h)) / np.max(np.abs(x64h)))
+        m_ms, f_ms = float(np.median(ms_m)), float(np.median(ms_64))
+        total_mixed += m_ms
+        total_fp64 += f_ms
+        per_d.append({"d": d, "mixed_ms": round(m_ms, 3), "fp64_factor_solve_ms": round(f_ms, 3),
+                      "iterations": it, "fallback": fb, "backward_error": bwd,
+                      "rel_diff_vs_fp64_solution": fwd, "fp64_info": int(info.item())})
+        del dab, db, x, l, x64
+        torch.cuda.empty_cache()
+    line = {
+        "metric": "mixed-precision band solve time n=1e5,k=1000,nrhs=8 (FP32 factor + FP64 refinement), sum over d=1..5",
+        "value": round(total_mixed, 3), "unit": "ms", "n_gpus": 1, "steps": 5, "warmup": 5,
+        "ms_per_step": round(total_mixed, 3), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "mixed-precision solve, n=%d, k=%d, nrhs=%d, A = L0 L0^T + 10^(-2d)||A|| I, "
+                               "L0 diagonal 10^U[-d,0], d = 1..5" % (n, k, nrhs),
+                   "fp64_factor_solve_ms_sum": round(total_fp64, 3), "per_d": per_d},
+    }
     print(json.dumps(line))
 
 

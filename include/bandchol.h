@@ -104,6 +104,33 @@ int64_t bandchol_tile(void);
 int64_t bandchol_set_walk_limit(int64_t kmax);
 
 /*
+ * FP32 factor: the same factorization in single precision (the trailing
+ * products on v_mfma_f32_16x16x4f32, FP32 accumulation), in place on a float
+ * band in the same layout.  Arguments and info as bandchol_factor_async
+ * (d_info: device int64; -5 when NULL).  Stream-ordered.
+ */
+int64_t bandchol_factor_f32(int64_t n, int64_t k, float* ab, int64_t ldab, int64_t* d_info, void* stream);
+
+/*
+ * Mixed-precision solve of A X = B: factor fl32(A) in FP32, then refine in
+ * FP64 (Buttari, Dongarra et al. 2007; LAPACK dsposv): x0 from the FP32
+ * factor, then repeat r = b - A x (FP64), d = A32^{-1} r (the FP32 factor
+ * widened to FP64), x += d, until every column has
+ * ||r||_inf <= sqrt(n) * 2^-53 * ||A||_inf * ||x||_inf.  Falls back to the
+ * FP64 factor and solve when the FP32 factor fails (fallback = 1), after 30
+ * corrections (2), or when a correction is not at most half the previous one
+ * in some column (3); 0 = no fallback.
+ *   ab (device, read only) -4 / ldab >= k+1 -5; b (device, n x nrhs) -6 /
+ *   ldb >= max(1,n) -7; x (device, n x nrhs, written) -8 / ldx -9; n -1, k -2,
+ *   nrhs -3.  iters, fallback: host pointers or NULL.
+ * Returns 0, or the info of the FP64 factor (> 0) if the fallback factor fails
+ * too.  Uses internal buffers of about 12 (k+1) n + 8 n nrhs bytes.
+ * Synchronous on the stream of bandchol_set_stream.
+ */
+int64_t bandchol_mixed_solve(int64_t n, int64_t k, int64_t nrhs, const double* ab, int64_t ldab, const double* b,
+                             int64_t ldb, double* x, int64_t ldx, int64_t* iters, int64_t* fallback);
+
+/*
  * Reverse mode of the solve, for a loss that depends on x = A^{-1} B through
  * an upstream gradient G = dloss/dX (n x nrhs): the gradient with respect to B
  * is A^{-1} G (A is symmetric), computed with two more band solves on the

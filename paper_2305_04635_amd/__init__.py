@@ -38,6 +38,8 @@ SIGNATURES = {
     "bandchol_solve_backward": (_I64, [_I64, _I64, _I64, _VP, _I64, _VP, _I64, _VP, _I64, _VP, _I64, _VP]),
     "bandchol_batch_set_adjoint": (_I64, [_VP, _VP, _VP, _VP]),
     "bandchol_batch_backward": (_I64, [_VP, _I64, _VP]),
+    "bandchol_factor_f32": (_I64, [_I64, _I64, _VP, _I64, _VP, _VP]),
+    "bandchol_mixed_solve": (_I64, [_I64, _I64, _I64, _VP, _I64, _VP, _I64, _VP, _I64, _VP, _VP]),
 }
 
 EHIP = -1000
@@ -139,6 +141,40 @@ def solve_async(ab, n, k, b, nrhs=None, ldab=None, ldb=None):
     rc = load().bandchol_solve_async(n, k, nrhs, ab.data_ptr(), ldab, b.data_ptr(), ldb, _stream())
     if rc != 0:
         _raise(rc, "bandchol_solve_async")
+
+
+FALLBACK_REASONS = {0: None, 1: "factor", 2: "iterations", 3: "stagnation"}
+
+
+def factor_f32(ab32, n, k, d_info, ldab=None):
+    """Stream-ordered FP32 factor of a float32 GPU band tensor; info to the int64 tensor d_info."""
+    import torch
+    ldab = k + 1 if ldab is None else ldab
+    if not isinstance(ab32, torch.Tensor) or ab32.dtype != torch.float32 or not ab32.is_cuda:
+        raise TypeError("ab32 must be a float32 GPU tensor")
+    rc = load().bandchol_factor_f32(n, k, ab32.data_ptr(), ldab, d_info.data_ptr(), _stream())
+    if rc != 0:
+        _raise(rc, "bandchol_factor_f32")
+
+
+def mixed_solve(ab, n, k, b, x, nrhs=None, ldab=None):
+    """Mixed-precision solve (FP32 factor + FP64 refinement): x <- A^{-1} b.
+    Returns (iterations, fallback reason or None)."""
+    ldab = k + 1 if ldab is None else ldab
+    for t, name in ((ab, "ab"), (b, "b"), (x, "x")):
+        _check_tensor(t, name)
+    nrhs = (b.numel() // max(n, 1)) if nrhs is None else nrhs
+    it, fb = ctypes.c_int64(), ctypes.c_int64()
+    lib = load()
+    lib.bandchol_set_stream(_stream())
+    ld = max(n, 1)
+    rc = lib.bandchol_mixed_solve(n, k, nrhs, ab.data_ptr(), ldab, b.data_ptr(), ld, x.data_ptr(), ld,
+                                  ctypes.byref(it), ctypes.byref(fb))
+    if rc < 0:
+        _raise(rc, "bandchol_mixed_solve")
+    if rc > 0:
+        raise BandCholError("matrix is not positive definite (info = %d)" % rc)
+    return int(it.value), FALLBACK_REASONS[int(fb.value)]
 
 
 def solve_backward(ab, n, k, x, g, gab, nrhs=None, ldab=None, ldgab=None):

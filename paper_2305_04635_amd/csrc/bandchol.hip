@@ -28,10 +28,14 @@
 
 #include "adjoint.h"
 #include "common.h"
+#include "mixed.h"
 #include "walk.h"
 
 size_t bandchol_solve_workspace(int64_t n);
 size_t bandchol_factor2_workspace(int64_t n, int64_t K);
+size_t bandchol_factor2_workspace_f32(int64_t n, int64_t K);
+hipError_t bandchol_factor2_launch_f32(int64_t n, int64_t k, float* ab, int64_t ldab, int64_t* d_info, void* ws,
+                                       int grid_max, hipStream_t st);
 hipError_t bandchol_factor2_launch(int64_t n, int64_t k, double* ab, int64_t ldab, int64_t* d_info, void* ws,
                                    int grid_max, hipStream_t st);
 hipError_t bandchol_solve_launch(int64_t n, int64_t k, int64_t nrhs, const double* ab, int64_t ldab, double* b,
@@ -59,6 +63,8 @@ struct DevWork {
   size_t size = 0;
   void* info_host = nullptr;  // pinned int64 for the synchronous calls
   void* info_dev = nullptr;   // device int64 for the synchronous calls (never reallocated)
+  void* mptr = nullptr;       // buffers of the mixed-precision solver (grown on demand)
+  size_t msize = 0;
 };
 std::mutex g_mu;
 std::vector<DevWork> g_work;
@@ -86,6 +92,30 @@ void* workspace(size_t bytes, hipError_t* err) {
     w.size = want;
   }
   return w.ptr;
+}
+
+// Buffers of the mixed-precision solver on the current device (grown on demand;
+// the caller synchronises before reusing them).
+void* mixed_buffers(size_t bytes, hipError_t* err) {
+  int dev = 0;
+  *err = hipGetDevice(&dev);
+  if (*err != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if ((int)g_work.size() <= dev) g_work.resize(dev + 1);
+  DevWork& w = g_work[dev];
+  if (w.msize < bytes) {
+    if (w.mptr) {
+      *err = hipDeviceSynchronize();
+      if (*err == hipSuccess) *err = hipFree(w.mptr);
+      w.mptr = nullptr;
+      w.msize = 0;
+      if (*err != hipSuccess) return nullptr;
+    }
+    *err = hipMalloc(&w.mptr, bytes);
+    if (*err != hipSuccess) { w.mptr = nullptr; return nullptr; }
+    w.msize = bytes;
+  }
+  return w.mptr;
 }
 
 // Host (pinned) and device int64 slots used by the synchronous factor call to
@@ -142,6 +172,8 @@ int walk_kmax() {
   }
   return g_walk_kmax;
 }
+
+constexpr int64_t MIXED_ITMAX = 30;   // refinement corrections before the FP64 fallback
 
 int spine_grid() {
   int grid = num_cus() * 2;
@@ -227,6 +259,152 @@ int64_t solve_async_impl(int64_t n, int64_t k, int64_t nrhs, const double* ab, i
   if (!ws) { set_err("workspace", e); return BANDCHOL_EHIP; }
   e = bandchol_solve_launch(n, kk, nrhs, ab, ldab, b, ldb, ws, num_cus(), st);
   if (e != hipSuccess) { set_err("solve launch", e); return BANDCHOL_EHIP; }
+  return 0;
+}
+
+int64_t factor_f32_impl(int64_t n, int64_t k, float* ab, int64_t ldab, int64_t* d_info, hipStream_t st) {
+  if (n < 0) return -1;
+  if (k < 0) return -2;
+  if (ab == nullptr && n > 0) return -3;
+  if (ldab < k + 1) return -4;
+  if (d_info == nullptr) return -5;
+  if (n > ((int64_t)1 << 31) - T) return -1;
+  hipError_t e;
+  if (n == 0) {
+    set_info_kernel<<<1, 1, 0, st>>>(d_info, 0);
+    e = hipGetLastError();
+    if (e != hipSuccess) { set_err("factor f32", e); return BANDCHOL_EHIP; }
+    return 0;
+  }
+  void* ws = workspace(bandchol_factor2_workspace_f32(n, tile_diagonals(n, k)), &e);
+  if (!ws) { set_err("workspace", e); return BANDCHOL_EHIP; }
+  e = bandchol_factor2_launch_f32(n, k, ab, ldab, d_info, ws, spine_grid(), st);
+  if (e != hipSuccess) { set_err("factor f32 launch", e); return BANDCHOL_EHIP; }
+  return 0;
+}
+
+double from_bits(unsigned long long u) {
+  double d;
+  memcpy(&d, &u, sizeof d);
+  return d;
+}
+
+// Mixed-precision solve (see bandchol.h).  Synchronous on `st`.
+int64_t mixed_solve_impl(int64_t n, int64_t k, int64_t nrhs, const double* ab, int64_t ldab, const double* b,
+                         int64_t ldb, double* x, int64_t ldx, int64_t* iters, int64_t* fallback, hipStream_t st) {
+  if (n < 0) return -1;
+  if (k < 0) return -2;
+  if (nrhs < 0) return -3;
+  if (ab == nullptr && n > 0) return -4;
+  if (ldab < k + 1) return -5;
+  if (b == nullptr && n > 0 && nrhs > 0) return -6;
+  if (ldb < (n > 1 ? n : 1)) return -7;
+  if (x == nullptr && n > 0 && nrhs > 0) return -8;
+  if (ldx < (n > 1 ? n : 1)) return -9;
+  if (iters) *iters = 0;
+  if (fallback) *fallback = 0;
+  if (n == 0 || nrhs == 0) return 0;
+  if (n > ((int64_t)1 << 31) - T) return -1;
+  const int64_t kk = k < n - 1 ? k : n - 1;
+  const int64_t ldl = kk + 1;
+  // buffers: L32 (float band), L (widened factor, or the FP64 factor on fallback),
+  // R (n x nrhs), norms (2 nrhs + 1), info
+  const size_t off_l32 = 0;
+  const size_t off_l = align_up(off_l32 + sizeof(float) * (size_t)ldl * n);
+  const size_t off_r = align_up(off_l + sizeof(double) * (size_t)ldl * n);
+  const size_t off_nrm = align_up(off_r + sizeof(double) * (size_t)n * nrhs);
+  const size_t off_info = align_up(off_nrm + sizeof(unsigned long long) * (size_t)(2 * nrhs + 1));
+  const size_t total = off_info + 256;
+  hipError_t e;
+  char* m = (char*)mixed_buffers(total, &e);
+  if (!m) { set_err("mixed buffers", e); return BANDCHOL_EHIP; }
+  float* l32 = (float*)(m + off_l32);
+  double* l = (double*)(m + off_l);
+  double* r = (double*)(m + off_r);
+  unsigned long long* nrm = (unsigned long long*)(m + off_nrm);
+  int64_t* dinfo = (int64_t*)(m + off_info);
+  std::vector<unsigned long long> hn(2 * nrhs + 1);
+  auto fail = [&](const char* what) {
+    set_err(what, e);
+    return (int64_t)BANDCHOL_EHIP;
+  };
+  auto fetch = [&](size_t count) -> bool {
+    e = hipMemcpyAsync(hn.data(), nrm, sizeof(unsigned long long) * count, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    return e == hipSuccess;
+  };
+  // ||A||_inf: row sums of |A| into R(:, 0), then their maximum
+  e = bandchol_residual(n, kk, ab, ldab, nullptr, 0, nullptr, 0, r, n, 1, 1, st);
+  if (e == hipSuccess) e = bandchol_colmax(n, 1, r, n, nrm + 2 * nrhs, st);
+  if (e != hipSuccess) return fail("mixed: norm");
+  // FP32 factor of fl32(A)
+  e = bandchol_band_to_f32(n, kk, ab, ldab, l32, ldl, st);
+  if (e != hipSuccess) return fail("mixed: convert");
+  int64_t rc = factor_f32_impl(n, kk, l32, ldl, dinfo, st);
+  if (rc != 0) return rc;
+  int64_t info32 = 0;
+  e = hipMemcpyAsync(&info32, dinfo, sizeof info32, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return fail("mixed: factor");
+  if (!fetch(2 * nrhs + 1)) return fail("mixed: norm");
+  const double anrm = from_bits(hn[2 * nrhs]);
+  const double tol = sqrt((double)n) * 0x1p-53 * anrm;
+  int64_t it = 0, reason = 0;
+  if (info32 != 0) reason = 1;
+  if (reason == 0) {
+    e = bandchol_band_to_f64(n, kk, l32, ldl, l, ldl, st);
+    if (e != hipSuccess) return fail("mixed: convert");
+    e = hipMemcpy2DAsync(x, sizeof(double) * ldx, b, sizeof(double) * ldb, sizeof(double) * n, nrhs,
+                         hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return fail("mixed: copy");
+    rc = solve_async_impl(n, kk, nrhs, l, ldl, x, ldx, st);
+    if (rc != 0) return rc;
+    std::vector<double> dprev(nrhs, 0.0);
+    for (;;) {
+      e = bandchol_residual(n, kk, ab, ldab, x, ldx, b, ldb, r, n, nrhs, 0, st);
+      if (e == hipSuccess) e = bandchol_colmax(n, nrhs, r, n, nrm, st);
+      if (e == hipSuccess) e = bandchol_colmax(n, nrhs, x, ldx, nrm + nrhs, st);
+      if (e != hipSuccess || !fetch(2 * nrhs)) return fail("mixed: residual");
+      bool done = true;
+      for (int64_t c = 0; c < nrhs; ++c)
+        if (!(from_bits(hn[c]) <= tol * from_bits(hn[nrhs + c]))) done = false;
+      if (done) break;
+      if (it == MIXED_ITMAX) { reason = 2; break; }
+      rc = solve_async_impl(n, kk, nrhs, l, ldl, r, n, st);
+      if (rc != 0) return rc;
+      e = bandchol_colmax(n, nrhs, r, n, nrm, st);
+      if (e != hipSuccess || !fetch(nrhs)) return fail("mixed: correction");
+      bool stall = false;
+      for (int64_t c = 0; c < nrhs; ++c)
+        if (it > 0 && !(from_bits(hn[c]) <= 0.5 * dprev[c])) stall = true;
+      if (stall) { reason = 3; break; }
+      for (int64_t c = 0; c < nrhs; ++c) dprev[c] = from_bits(hn[c]);
+      e = bandchol_axpy(n, nrhs, x, ldx, r, n, st);
+      if (e != hipSuccess) return fail("mixed: update");
+      ++it;
+    }
+  }
+  if (iters) *iters = it;
+  if (fallback) *fallback = reason;
+  if (reason == 0) return 0;
+  // FP64 fallback: factor a copy of A into L, then solve
+  e = hipMemcpy2DAsync(l, sizeof(double) * ldl, ab, sizeof(double) * ldab, sizeof(double) * ldl, n,
+                       hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return fail("mixed: copy");
+  rc = factor_async_impl(n, kk, l, ldl, dinfo, st);
+  if (rc != 0) return rc;
+  int64_t info64 = 0;
+  e = hipMemcpyAsync(&info64, dinfo, sizeof info64, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return fail("mixed: fallback factor");
+  if (info64 != 0) return info64;
+  e = hipMemcpy2DAsync(x, sizeof(double) * ldx, b, sizeof(double) * ldb, sizeof(double) * n, nrhs,
+                       hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return fail("mixed: copy");
+  rc = solve_async_impl(n, kk, nrhs, l, ldl, x, ldx, st);
+  if (rc != 0) return rc;
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return fail("mixed: fallback solve");
   return 0;
 }
 
@@ -331,12 +509,24 @@ void bandchol_finalize(void) {
     if (g_work[d].ptr) (void)hipFree(g_work[d].ptr);
     if (g_work[d].info_dev) (void)hipFree(g_work[d].info_dev);
     if (g_work[d].info_host) (void)hipHostFree(g_work[d].info_host);
+    if (g_work[d].mptr) (void)hipFree(g_work[d].mptr);
     g_work[d] = DevWork();
   }
   (void)hipSetDevice(cur);
 }
 
 int64_t bandchol_tile(void) { return T; }
+
+int64_t bandchol_factor_f32(int64_t n, int64_t k, float* ab, int64_t ldab, int64_t* d_info, void* stream) {
+  g_err[0] = 0;
+  return factor_f32_impl(n, k, ab, ldab, d_info, (hipStream_t)stream);
+}
+
+int64_t bandchol_mixed_solve(int64_t n, int64_t k, int64_t nrhs, const double* ab, int64_t ldab, const double* b,
+                             int64_t ldb, double* x, int64_t ldx, int64_t* iters, int64_t* fallback) {
+  g_err[0] = 0;
+  return mixed_solve_impl(n, k, nrhs, ab, ldab, b, ldb, x, ldx, iters, fallback, g_stream);
+}
 
 int64_t bandchol_solve_backward(int64_t n, int64_t k, int64_t nrhs, const double* ab, int64_t ldab, const double* x,
                                 int64_t ldx, double* g, int64_t ldg, double* gab, int64_t ldgab, void* stream) {

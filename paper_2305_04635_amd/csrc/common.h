@@ -1,9 +1,15 @@
-// Device building blocks shared by the band Cholesky kernels (gfx950, FP64).
+// Device building blocks shared by the band Cholesky kernels (gfx950), for
+// FP64 and FP32 data.
 //
 // Tiles are T x T (T = 32).  A tile held by a workgroup of 4 waves is split in
-// 16 x 16 blocks; in MFMA accumulator form lane l, register r of a block holds
-// the element (row l%16, column 4r + l/16), so that consecutive lanes are
+// 16 x 16 blocks.  MFMA operands use the fragment form "lane l holds
+// M[16*blk + l%16][k0 + l/16]" (the same for both precisions); results come
+// back in the accumulator form: lane l, register r holds the element (row
+// l%16, column acc_col0(l) + ACC_STEP*r), so that consecutive lanes are
 // consecutive rows — consecutive addresses in the column-major band layout.
+// The column mapping differs between the two instructions used:
+//   v_mfma_f64_16x16x4f64  column 4r + l/16     (ACC_STEP 4)
+//   v_mfma_f32_16x16x4f32  column 4(l/16) + r   (ACC_STEP 1)
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -14,31 +20,57 @@ constexpr int T = 32;       // tile width
 constexpr int LP = T + 1;   // LDS pitch of a staged tile (column-major)
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
-// LDS pointers keep their address space across function boundaries, so that
-// separately compiled device functions still address LDS with ds_* instructions.
-typedef __attribute__((address_space(3))) double lds_d;
-typedef __attribute__((address_space(3))) int lds_i;
+// LDS and global pointers keep their address space across function
+// boundaries, so that separately compiled device functions still use ds_* and
+// global_* instructions (not flat ones).
+template <typename F> using lds_t = __attribute__((address_space(3))) F;
+template <typename F> using glb_t = __attribute__((address_space(1))) F;
+typedef lds_t<double> lds_d;
+typedef lds_t<int> lds_i;
+typedef glb_t<double> glb_d;
+typedef glb_t<int> glb_i;
+
+template <typename F> struct Prec;
+template <> struct Prec<double> {
+  typedef d4 v4;
+  static constexpr int ACC_STEP = 4;
+  __device__ static __forceinline__ int acc_col0(int lane) { return lane >> 4; }
+};
+template <> struct Prec<float> {
+  typedef f4 v4;
+  static constexpr int ACC_STEP = 1;
+  __device__ static __forceinline__ int acc_col0(int lane) { return 4 * (lane >> 4); }
+};
+template <typename F> using v4_t = typename Prec<F>::v4;
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
-__device__ __forceinline__ double readlane_d(double v, int lane) {
+__device__ __forceinline__ double readlane(double v, int lane) {
   int2 p = __builtin_bit_cast(int2, v);
   p.x = __builtin_amdgcn_readlane(p.x, lane);
   p.y = __builtin_amdgcn_readlane(p.y, lane);
   return __builtin_bit_cast(double, p);
 }
+__device__ __forceinline__ float readlane(float v, int lane) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
+__device__ __forceinline__ double readlane_d(double v, int lane) { return readlane(v, lane); }
 
-// D += X Y^T on one 16x16 block, fragments "lane l holds M[16*blk + l%16][k0 + l/16]".
-// The operand order puts the result in the layout described above
-// (v_mfma_f64_16x16x4 returns D[4r + l/16][l%16] in lane l, register r).
+// D += X Y^T on one 16x16 block from fragments of X and Y; the operand order
+// (Y first) puts the result in the accumulator form described above.
 __device__ __forceinline__ d4 mfma_xyt(double xf, double yf, d4 acc) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(yf, xf, acc, 0, 0, 0);
 }
+__device__ __forceinline__ f4 mfma_xyt(float xf, float yf, f4 acc) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(yf, xf, acc, 0, 0, 0);
+}
 
-// 1/d from the hardware estimate (about 24 bits) and two Newton-Raphson steps
-// r <- r + r (1 - d r), each doubling the correct bits; exact for powers of two.
+// 1/d from the hardware estimate and Newton-Raphson steps r <- r + r (1 - d r),
+// each doubling the correct bits; exact for powers of two.  FP64: the estimate
+// carries about 24 bits, two steps; FP32: the estimate is within an ulp, one step.
 __device__ __forceinline__ double recip(double d) {
   double r = __builtin_amdgcn_rcp(d);
   double e = fma(-d, r, 1.0);
@@ -46,40 +78,50 @@ __device__ __forceinline__ double recip(double d) {
   e = fma(-d, r, 1.0);
   return fma(r, e, r);
 }
+__device__ __forceinline__ float recip(float d) {
+  const float r = __builtin_amdgcn_rcpf(d);
+  const float e = fmaf(-d, r, 1.0f);
+  return fmaf(r, e, r);
+}
+
+__device__ __forceinline__ double prec_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float prec_sqrt(float x) { return sqrtf(x); }
 
 // Wait until this wave's outstanding vector memory operations (loads and
 // stores) have completed.
 __device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
-typedef __attribute__((address_space(1))) double glb_d;
-typedef __attribute__((address_space(1))) int glb_i;
-
 // Relaxed agent-scope atomic accesses: coherent across the chip's L2 caches
 // without cache maintenance; used for data that other workgroups read.
-__device__ __forceinline__ double aload(const glb_d* p) {
+template <typename F>
+__device__ __forceinline__ F aload(const glb_t<F>* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void astore(glb_d* p, double v) {
+template <typename F>
+__device__ __forceinline__ void astore(glb_t<F>* p, F v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-struct Band {
-  glb_d* ab;
+template <typename F>
+struct BandT {
+  glb_t<F>* ab;
   int64_t n, k, ldab;
   __device__ __forceinline__ bool in_band(int64_t i, int64_t j) const {
     const int64_t d = i - j;
     return i < n && d >= 0 && d <= k;
   }
-  __device__ __forceinline__ glb_d* at(int64_t i, int64_t j) const { return ab + (i - j) + j * ldab; }
-  __device__ __forceinline__ double ld(int64_t i, int64_t j) const { return in_band(i, j) ? *at(i, j) : 0.0; }
+  __device__ __forceinline__ glb_t<F>* at(int64_t i, int64_t j) const { return ab + (i - j) + j * ldab; }
+  __device__ __forceinline__ F ld(int64_t i, int64_t j) const { return in_band(i, j) ? *at(i, j) : F(0); }
 };
+typedef BandT<double> Band;
 
 // A lane's run of band elements A(i, j0 + cs*q), q = 0, 1, ...: the first at p,
-// the next ones cs*(ldab-1) doubles apart (A(i, j) sits at ab + i + j*(ldab-1)).
+// the next ones cs*(ldab-1) elements apart (A(i, j) sits at ab + i + j*(ldab-1)).
 // Element q is in the band iff i < n and 0 <= d0 - cs*q <= k.  Set up once per
 // tile so that each element costs one compare and one pointer step.
-struct Run {
-  glb_d* p;
+template <typename F>
+struct RunT {
+  glb_t<F>* p;
   int64_t step;
   int d0, ds, k;
   bool row_ok;
@@ -87,13 +129,15 @@ struct Run {
     const int d = d0 - ds * q;
     return row_ok && d >= 0 && d <= k;
   }
-  __device__ __forceinline__ glb_d* at(int q) const { return p + step * q; }
-  __device__ __forceinline__ double ld(int q) const { return in(q) ? *at(q) : 0.0; }
-  __device__ __forceinline__ double ald(int q) const { return in(q) ? aload(at(q)) : 0.0; }
+  __device__ __forceinline__ glb_t<F>* at(int q) const { return p + step * q; }
+  __device__ __forceinline__ F ld(int q) const { return in(q) ? *at(q) : F(0); }
+  __device__ __forceinline__ F ald(int q) const { return in(q) ? aload<F>(at(q)) : F(0); }
 };
+typedef RunT<double> Run;
 
-__device__ __forceinline__ Run band_run(const Band& a, int64_t i, int64_t j0, int cs) {
-  Run r;
+template <typename F>
+__device__ __forceinline__ RunT<F> band_run(const BandT<F>& a, int64_t i, int64_t j0, int cs) {
+  RunT<F> r;
   r.p = a.ab + i + j0 * (a.ldab - 1);
   r.step = (int64_t)cs * (a.ldab - 1);
   r.d0 = (int)(i - j0);
@@ -103,26 +147,33 @@ __device__ __forceinline__ Run band_run(const Band& a, int64_t i, int64_t j0, in
   return r;
 }
 
+// The run of accumulator-form elements of block (bi, bj) of tile (R, C) for this lane.
+template <typename F>
+__device__ __forceinline__ RunT<F> acc_run(const BandT<F>& a, int64_t R, int64_t C, int bi, int bj) {
+  const int lane = lane_id();
+  return band_run(a, R * T + 16 * bi + (lane & 15), C * T + 16 * bj + Prec<F>::acc_col0(lane), Prec<F>::ACC_STEP);
+}
+
 // ---------------------------------------------------------------- tile blocks in global memory
 
 // Block (bi, bj) of tile (R, C) into accumulator form.  On a diagonal tile the
 // positions past row n-1 get an identity so that the factorization there is trivial.
-__device__ __forceinline__ d4 blk_load(const Band& a, int64_t R, int64_t C, int bi, int bj) {
-  const int lane = lane_id();
-  const Run run = band_run(a, R * T + 16 * bi + (lane & 15), C * T + 16 * bj + (lane >> 4), 4);
-  d4 acc;
+template <typename F>
+__device__ __forceinline__ v4_t<F> blk_load(const BandT<F>& a, int64_t R, int64_t C, int bi, int bj) {
+  const RunT<F> run = acc_run(a, R, C, bi, bj);
+  v4_t<F> acc;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    double v = run.ld(r);
-    if (R == C && !run.row_ok && run.d0 - 4 * r == 0) v = 1.0;
+    F v = run.ld(r);
+    if (R == C && !run.row_ok && run.d0 - run.ds * r == 0) v = F(1);
     acc[r] = v;
   }
   return acc;
 }
 
-__device__ __forceinline__ void blk_store(const Band& a, int64_t R, int64_t C, int bi, int bj, d4 v) {
-  const int lane = lane_id();
-  const Run run = band_run(a, R * T + 16 * bi + (lane & 15), C * T + 16 * bj + (lane >> 4), 4);
+template <typename F>
+__device__ __forceinline__ void blk_store(const BandT<F>& a, int64_t R, int64_t C, int bi, int bj, v4_t<F> v) {
+  const RunT<F> run = acc_run(a, R, C, bi, bj);
 #pragma unroll
   for (int r = 0; r < 4; ++r)
     if (run.in(r)) *run.at(r) = v[r];
@@ -130,14 +181,31 @@ __device__ __forceinline__ void blk_store(const Band& a, int64_t R, int64_t C, i
 
 // ---------------------------------------------------------------- tiles staged in LDS (column-major, pitch LP)
 
-__device__ __forceinline__ void blk_to_lds(lds_d* s, int bi, int bj, d4 v) {
+// LDS index of accumulator element r of block (bi, bj) for this lane.
+template <typename F>
+__device__ __forceinline__ int acc_lds_index(int bi, int bj, int r) {
   const int lane = lane_id();
+  return (16 * bj + Prec<F>::acc_col0(lane) + Prec<F>::ACC_STEP * r) * LP + 16 * bi + (lane & 15);
+}
+
+template <typename F>
+__device__ __forceinline__ void blk_to_lds(lds_t<F>* s, int bi, int bj, v4_t<F> v) {
 #pragma unroll
-  for (int r = 0; r < 4; ++r) s[(16 * bj + 4 * r + (lane >> 4)) * LP + 16 * bi + (lane & 15)] = v[r];
+  for (int r = 0; r < 4; ++r) s[acc_lds_index<F>(bi, bj, r)] = v[r];
+}
+
+template <typename F>
+__device__ __forceinline__ v4_t<F> blk_from_lds(const lds_t<F>* s, int bi, int bj) {
+  v4_t<F> v;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) v[r] = s[acc_lds_index<F>(bi, bj, r)];
+  return v;
 }
 
 // acc -= X_blk(bi) Y_blk(bj)^T, X and Y tiles in LDS (column-major, pitch LP).
-__device__ __forceinline__ d4 blk_gemm_lds(const lds_d* x, const lds_d* y, int bi, int bj, d4 acc, int qmax = T / 4) {
+template <typename F>
+__device__ __forceinline__ v4_t<F> blk_gemm_lds(const lds_t<F>* x, const lds_t<F>* y, int bi, int bj, v4_t<F> acc,
+                                               int qmax = T / 4) {
   const int lane = lane_id();
 #pragma unroll
   for (int q = 0; q < T / 4; ++q) {
@@ -151,9 +219,11 @@ __device__ __forceinline__ d4 blk_gemm_lds(const lds_d* x, const lds_d* y, int b
 
 // out = X_blk(bi) * L^{-T}, X in LDS (column-major), L^{-T} row-major T x T in LDS
 // with row pitch `pitch` (upper triangular, so k-steps past column 16*bj+15 are zero).
-__device__ __forceinline__ d4 blk_trsm_lds(const lds_d* x, const lds_d* linvt, int bi, int bj, int pitch = T) {
+template <typename F>
+__device__ __forceinline__ v4_t<F> blk_trsm_lds(const lds_t<F>* x, const lds_t<F>* linvt, int bi, int bj,
+                                               int pitch = T) {
   const int lane = lane_id();
-  d4 out = {0, 0, 0, 0};
+  v4_t<F> out = {0, 0, 0, 0};
   const int qmax = 4 * bj + 4;
 #pragma unroll
   for (int q = 0; q < T / 4; ++q) {
@@ -174,98 +244,44 @@ __device__ __forceinline__ d4 blk_trsm_lds(const lds_d* x, const lds_d* linvt, i
 // w_ij = A'(i, j) is final once column j-1 has been applied; it is broadcast
 // with readlane (no LDS traffic, so the sweep does not queue behind the MFMA
 // operand reads of the other waves) and every row is updated by
-// A'(i, l) -= (w_ij / d_j) w_lj, l > j.  Only one division per column is on the
-// dependency chain: the next pivot d_{j+1} = A'(j+1,j+1) - w_{j+1,j}^2 / d_j is
-// formed directly from two values known before the division.  The square roots
-// are taken once at the end, off the chain: both the factor rows (unit factor
-// l, L = l D^{1/2}) and the identity rows (which now hold l^{-T} D^{-1}, and
-// L^{-T} = l^{-T} D^{-1/2}) are scaled column by column by sqrt(d_c).
+// A'(i, l) -= (w_ij / d_j) w_lj, l > j.  Only one reciprocal per column is on
+// the dependency chain: the next pivot d_{j+1} = A'(j+1,j+1) - w_{j+1,j}^2 / d_j
+// is formed directly from two values known before the reciprocal.  The square
+// roots are taken once at the end, off the chain: both the factor rows (unit
+// factor l, L = l D^{1/2}) and the identity rows (which now hold l^{-T} D^{-1},
+// and L^{-T} = l^{-T} D^{-1/2}) are scaled column by column by sqrt(d_c).
 // Afterwards lane i < T holds row i of L (upper part unspecified) and lane
 // T+b holds row b of L^{-T}.  Returns the first local column whose pivot is
 // not > 0 (zero, negative or NaN), or -1.
-__device__ __forceinline__ int sweep_ldlt(double (&row)[T], lds_d* wbuf) {
-  (void)wbuf;
+template <typename F>
+__device__ __forceinline__ int sweep_ldlt(F (&row)[T]) {
   const int lane = lane_id();
-  double d_mine = 1.0;                    // lane c keeps pivot c
-  double dcur = readlane_d(row[0], 0);
+  F d_mine = F(1);                        // lane c keeps pivot c
+  F dcur = readlane(row[0], 0);
   int fail = -1;
   // Straight-line code (no exit per column) so that the scheduler can overlap
   // column j+1's pivot chain with column j's row updates.
 #pragma unroll
   for (int j = 0; j < T; ++j) {
-    const double d = dcur;
-    fail = (fail < 0 && !(d > 0.0)) ? j : fail;
-    const double w = row[j];
-    double p = 0.0, wn = 0.0;
+    const F d = dcur;
+    fail = (fail < 0 && !(d > F(0))) ? j : fail;
+    const F w = row[j];
+    F p = F(0), wn = F(0);
     if (j + 1 < T) {
-      p = readlane_d(row[j + 1], j + 1);
-      wn = readlane_d(w, j + 1);
+      p = readlane(row[j + 1], j + 1);
+      wn = readlane(w, j + 1);
     }
-    const double dinv = recip(d);
+    const F dinv = recip(d);
     d_mine = (lane == j) ? d : d_mine;
     if (j + 1 < T) dcur = fma(-(wn * wn), dinv, p);
-    const double q = w * dinv;
-    row[j] = (lane == j) ? 1.0 : q;
+    const F q = w * dinv;
+    row[j] = (lane == j) ? F(1) : q;
 #pragma unroll
-    for (int l = j + 1; l < T; ++l) row[l] = fma(-q, readlane_d(w, l), row[l]);
+    for (int l = j + 1; l < T; ++l) row[l] = fma(-q, readlane(w, l), row[l]);
   }
-  const double s_mine = sqrt(d_mine);
+  const F s_mine = prec_sqrt(d_mine);
 #pragma unroll
-  for (int c = 0; c < T; ++c) row[c] *= readlane_d(s_mine, c);
-  return fail;
-}
-
-// The same sweep, with the column broadcast through LDS instead of readlane:
-// every lane stores its w_ij, and the values w_lj (l > j) come back two at a
-// time with 16-byte broadcast reads (all lanes read the same address).  The
-// two values on the pivot chain (the next pivot and its multiplier) still use
-// readlane.  wbuf: 2 x 64 doubles of LDS, 16-byte aligned, private to the wave.
-typedef double d2 __attribute__((ext_vector_type(2)));
-typedef __attribute__((address_space(3))) d2 lds_d2;
-
-__device__ __forceinline__ int sweep_ldlt_lds(double (&row)[T], lds_d* wbuf) {
-  const int lane = lane_id();
-  double d_mine = 1.0;
-  double dcur = readlane_d(row[0], 0);
-  int fail = -1;
-#pragma unroll
-  for (int j = 0; j < T; ++j) {
-    lds_d* wb = wbuf + 64 * (j & 1);
-    const double d = dcur;
-    fail = (fail < 0 && !(d > 0.0)) ? j : fail;
-    const double w = row[j];
-    wb[lane] = w;
-    double p = 0.0, wn = 0.0;
-    if (j + 1 < T) {
-      p = readlane_d(row[j + 1], j + 1);
-      wn = readlane_d(w, j + 1);
-    }
-    const double dinv = recip(d);
-    d_mine = (lane == j) ? d : d_mine;
-    if (j + 1 < T) dcur = fma(-(wn * wn), dinv, p);
-    const double q = w * dinv;
-    row[j] = (lane == j) ? 1.0 : q;
-    const lds_d2* wb2 = (const lds_d2*)wb;
-#pragma unroll
-    for (int l = j + 1; l < T; ++l) {
-      double wl;
-      if ((l & 1) == 0 && l + 1 < T) {
-        const d2 v = wb2[l >> 1];
-        wl = v.x;
-        row[l + 1] = fma(-q, v.y, row[l + 1]);
-      } else if ((l & 1) == 1 && l == j + 1) {
-        wl = wb[l];
-      } else if ((l & 1) == 1) {
-        continue;  // done with its even partner
-      } else {
-        wl = wb[l];
-      }
-      row[l] = fma(-q, wl, row[l]);
-    }
-  }
-  const double s_mine = sqrt(d_mine);
-#pragma unroll
-  for (int c = 0; c < T; ++c) row[c] *= readlane_d(s_mine, c);
+  for (int c = 0; c < T; ++c) row[c] *= readlane(s_mine, c);
   return fail;
 }
 

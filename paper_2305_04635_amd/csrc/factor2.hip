@@ -1,4 +1,5 @@
-// Multi-workgroup band Cholesky for wide bands (gfx950, FP64).
+// Multi-workgroup band Cholesky for wide bands (gfx950; FP64, and FP32 for the
+// mixed-precision solver).
 //
 // Tiles T x T down the band, tile (R, C) for 0 <= R - C <= K.  One workgroup,
 // the spine (whoever takes ticket 0), carries the dependency chain along the
@@ -32,21 +33,23 @@ constexpr int NT = 256;
 constexpr long long SPIN_LIMIT = 1LL << 22;
 
 
+template <typename F>
 struct Ws {
   glb_i* tflag;     // NB*(K+1): tile (R, R-d) published, index R*(K+1)+d
   glb_i* hflag;     // NB: pre-accumulated tiles of step m-1 published
-  glb_d* linvt;     // NB*T*T: L(C,C)^{-T}, row-major
-  glb_d* pre;       // NB*2*T*T: per m, tile (m,m-1) then tile (m,m), column-major
+  glb_t<F>* linvt;  // NB*T*T: L(C,C)^{-T}, row-major
+  glb_t<F>* pre;    // NB*2*T*T: per m, tile (m,m-1) then tile (m,m), column-major
   unsigned* queue;
   glb_i* abort_flag;  // 1 = pivot failure, 2 = wait bound exceeded
   unsigned long long* first_fail;
 };
 
+template <typename F>
 struct Args {
-  Band a;
+  BandT<F> a;
   int NB, K;
   unsigned ntickets;
-  Ws w;
+  Ws<F> w;
 };
 
 __device__ __forceinline__ int aflag(const glb_i* p) {
@@ -55,7 +58,8 @@ __device__ __forceinline__ int aflag(const glb_i* p) {
 __device__ __forceinline__ void raise_flag(glb_i* p) { __hip_atomic_store(p, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 
 // This wave waits for *f (bounded); every lane gets the same answer.
-__device__ __forceinline__ bool wave_wait(const glb_i* f, const Ws& w) {
+template <typename F>
+__device__ __forceinline__ bool wave_wait(const glb_i* f, const Ws<F>& w) {
   glb_i* const abort_flag = w.abort_flag;
   long long spins = 0;
   while (!aflag(f)) {
@@ -70,54 +74,62 @@ __device__ __forceinline__ bool wave_wait(const glb_i* f, const Ws& w) {
   return true;
 }
 
-__device__ __forceinline__ int tidx(const Args& A, int64_t R, int64_t C) { return (int)(R * (A.K + 1) + (R - C)); }
+template <typename F>
+__device__ __forceinline__ int tidx(const Args<F>& A, int64_t R, int64_t C) { return (int)(R * (A.K + 1) + (R - C)); }
 
 // ---------------------------------------------------------------- block I/O with atomics
 
 // Block (bi, bj) of tile (R, C) in accumulator form (see common.h).  On a
 // diagonal tile the positions past row n-1 get an identity.
-__device__ __forceinline__ d4 ablk_load(const Band& a, int64_t R, int64_t C, int bi, int bj) {
-  const int lane = lane_id();
-  const Run run = band_run(a, R * T + 16 * bi + (lane & 15), C * T + 16 * bj + (lane >> 4), 4);
-  d4 acc;
+template <typename F>
+__device__ __forceinline__ v4_t<F> ablk_load(const BandT<F>& a, int64_t R, int64_t C, int bi, int bj) {
+  const RunT<F> run = acc_run(a, R, C, bi, bj);
+  v4_t<F> acc;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    double v = run.ald(r);
-    if (R == C && !run.row_ok && run.d0 - 4 * r == 0) v = 1.0;
+    F v = run.ald(r);
+    if (R == C && !run.row_ok && run.d0 - run.ds * r == 0) v = F(1);
     acc[r] = v;
   }
   return acc;
 }
 
-__device__ __forceinline__ void ablk_store(const Band& a, int64_t R, int64_t C, int bi, int bj, d4 v) {
-  const int lane = lane_id();
-  const Run run = band_run(a, R * T + 16 * bi + (lane & 15), C * T + 16 * bj + (lane >> 4), 4);
+template <typename F>
+__device__ __forceinline__ void ablk_store(const BandT<F>& a, int64_t R, int64_t C, int bi, int bj, v4_t<F> v) {
+  const RunT<F> run = acc_run(a, R, C, bi, bj);
 #pragma unroll
   for (int r = 0; r < 4; ++r)
     if (run.in(r)) astore(run.at(r), v[r]);
 }
 
-// A dense T x T tile in column-major workspace memory.
-__device__ __forceinline__ d4 wblk_load(const glb_d* t, int bi, int bj) {
+// A dense T x T tile in column-major workspace memory, in accumulator form.
+template <typename F>
+__device__ __forceinline__ int wblk_index(int bi, int bj, int r) {
   const int lane = lane_id();
-  d4 v;
+  return (16 * bj + Prec<F>::acc_col0(lane) + Prec<F>::ACC_STEP * r) * T + 16 * bi + (lane & 15);
+}
+template <typename F>
+__device__ __forceinline__ v4_t<F> wblk_load(const glb_t<F>* t, int bi, int bj) {
+  v4_t<F> v;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) v[r] = aload(t + (16 * bj + 4 * r + (lane >> 4)) * T + 16 * bi + (lane & 15));
+  for (int r = 0; r < 4; ++r) v[r] = aload<F>(t + wblk_index<F>(bi, bj, r));
   return v;
 }
-__device__ __forceinline__ void wblk_store(glb_d* t, int bi, int bj, d4 v) {
-  const int lane = lane_id();
+template <typename F>
+__device__ __forceinline__ void wblk_store(glb_t<F>* t, int bi, int bj, v4_t<F> v) {
 #pragma unroll
-  for (int r = 0; r < 4; ++r) astore(t + (16 * bj + 4 * r + (lane >> 4)) * T + 16 * bi + (lane & 15), v[r]);
+  for (int r = 0; r < 4; ++r) astore<F>(t + wblk_index<F>(bi, bj, r), v[r]);
 }
 
 // acc -= X_blk(bi) Y_blk(bj)^T with X = tile (Rx, s), Y = tile (Ry, s) from the band.
-__device__ __forceinline__ d4 aterm(const Band& a, int64_t Rx, int64_t Ry, int64_t s, int bi, int bj, d4 acc) {
+template <typename F>
+__device__ __forceinline__ v4_t<F> aterm(const BandT<F>& a, int64_t Rx, int64_t Ry, int64_t s, int bi, int bj,
+                                         v4_t<F> acc) {
   const int lane = lane_id();
   const int64_t j0 = s * T + (lane >> 4);
-  const Run x = band_run(a, Rx * T + 16 * bi + (lane & 15), j0, 4);
-  const Run y = band_run(a, Ry * T + 16 * bj + (lane & 15), j0, 4);
-  double xf[T / 4], yf[T / 4];
+  const RunT<F> x = band_run(a, Rx * T + 16 * bi + (lane & 15), j0, 4);
+  const RunT<F> y = band_run(a, Ry * T + 16 * bj + (lane & 15), j0, 4);
+  F xf[T / 4], yf[T / 4];
 #pragma unroll
   for (int q = 0; q < T / 4; ++q) {
     xf[q] = x.ald(q);
@@ -132,7 +144,9 @@ __device__ __forceinline__ d4 aterm(const Band& a, int64_t Rx, int64_t Ry, int64
 
 // Apply the terms s in [s0, s1) of tile (R, C) (blocks of this wave), in runs
 // of published operand tiles.  Xrow = R, Yrow = C.
-__device__ __forceinline__ bool apply_terms(const Args& A, int64_t R, int64_t C, int64_t s0, int64_t s1, int bi, int bj, d4& acc) {
+template <typename F>
+__device__ __forceinline__ bool apply_terms(const Args<F>& A, int64_t R, int64_t C, int64_t s0, int64_t s1, int bi, int bj,
+                                            v4_t<F>& acc) {
   for (int64_t s = s0; s < s1; ++s) {
     // operands: tile (R, s) and tile (C, s); spine tiles (d = 1) and helper tiles share one flag array
     if (!wave_wait(&A.w.tflag[tidx(A, R, s)], A.w)) return false;
@@ -143,13 +157,15 @@ __device__ __forceinline__ bool apply_terms(const Args& A, int64_t R, int64_t C,
 }
 
 // Trsm of the accumulator tile held across the 4 waves: out = acc * L(C,C)^{-T}.
-__device__ __forceinline__ d4 trsm_from_lds(const lds_d* x, const glb_d* linvt_g, int bi, int bj) {
+template <typename F>
+__device__ __forceinline__ v4_t<F> trsm_from_lds(const lds_t<F>* x, const glb_t<F>* linvt_g, int bi, int bj) {
   const int lane = lane_id();
-  d4 out = {0, 0, 0, 0};
+  v4_t<F> out = {0, 0, 0, 0};
   const int qmax = 4 * bj + 4;
-  double yf[T / 4];
+  F yf[T / 4];
 #pragma unroll
-  for (int q = 0; q < T / 4; ++q) yf[q] = (q < qmax) ? aload(linvt_g + (4 * q + (lane >> 4)) * T + 16 * bj + (lane & 15)) : 0.0;
+  for (int q = 0; q < T / 4; ++q)
+    yf[q] = (q < qmax) ? aload<F>(linvt_g + (4 * q + (lane >> 4)) * T + 16 * bj + (lane & 15)) : F(0);
 #pragma unroll
   for (int q = 0; q < T / 4; ++q)
     if (q < qmax) out = mfma_xyt(x[(4 * q + (lane >> 4)) * LP + 16 * bi + (lane & 15)], yf[q], out);
@@ -159,11 +175,13 @@ __device__ __forceinline__ d4 trsm_from_lds(const lds_d* x, const glb_d* linvt_g
 // The noinline functions below copy their structure arguments into locals
 // first: the references point at a stack copy, and after every atomic store or
 // fence the fields would otherwise be re-read from memory.
-__device__ __attribute__((noinline)) void task_off(const Args& A_, int64_t R, int64_t C, lds_d* stage, lds_i* s_ok) {
-  const Args A = A_;
+template <typename F>
+__device__ __attribute__((noinline)) void task_off(const Args<F>& A_, int64_t R, int64_t C, lds_t<F>* stage,
+                                                   lds_i* s_ok) {
+  const Args<F> A = A_;
   const int wave = wave_id();
   const int bi = wave & 1, bj = wave >> 1;
-  d4 acc = ablk_load(A.a, R, C, bi, bj);
+  v4_t<F> acc = ablk_load(A.a, R, C, bi, bj);
   const int64_t s0 = R - A.K > 0 ? R - A.K : 0;
   int ok = apply_terms(A, R, C, s0, C, bi, bj, acc) ? 1 : 0;
   if (ok) ok = wave_wait(&A.w.tflag[tidx(A, C, C)], A.w) ? 1 : 0;
@@ -171,7 +189,7 @@ __device__ __attribute__((noinline)) void task_off(const Args& A_, int64_t R, in
   if (!ok && lane_id() == 0) *s_ok = 0;
   __syncthreads();
   if (*s_ok == 0) return;
-  const d4 out = trsm_from_lds(stage, A.w.linvt + C * T * T, bi, bj);
+  const v4_t<F> out = trsm_from_lds<F>(stage, A.w.linvt + C * T * T, bi, bj);
   ablk_store(A.a, R, C, bi, bj, out);
   wait_vmem();
   __syncthreads();
@@ -179,20 +197,21 @@ __device__ __attribute__((noinline)) void task_off(const Args& A_, int64_t R, in
 }
 
 // Pre-accumulate the spine's tiles of step m-1: (m, m-1) and (m, m), terms s <= m-3.
-__device__ __attribute__((noinline)) void task_pre(const Args& A_, int64_t m, lds_i* s_ok) {
-  const Args A = A_;
+template <typename F>
+__device__ __attribute__((noinline)) void task_pre(const Args<F>& A_, int64_t m, lds_i* s_ok) {
+  const Args<F> A = A_;
   const int wave = wave_id();
   const int64_t s0 = m - A.K > 0 ? m - A.K : 0;
-  glb_d* po = A.w.pre + m * 2 * T * T;
-  glb_d* pd = po + T * T;
+  glb_t<F>* po = A.w.pre + m * 2 * T * T;
+  glb_t<F>* pd = po + T * T;
   // waves 0-3: one block of (m, m-1) each; waves 1-3 also one lower block of
   // (m, m).  Both blocks of a wave take each term as soon as its operands are
   // published, so that only the last term is left once the last one arrives.
   int ok = 1;
   const int bi = wave & 1, bj = wave >> 1;
   const int di = (wave >= 2), dj = (wave == 3);
-  d4 acc = ablk_load(A.a, m, m - 1, bi, bj);
-  d4 accd = {0, 0, 0, 0};
+  v4_t<F> acc = ablk_load(A.a, m, m - 1, bi, bj);
+  v4_t<F> accd = {0, 0, 0, 0};
   if (wave >= 1) accd = ablk_load(A.a, m, m, di, dj);
   for (int64_t s = s0; s < m - 2; ++s) {
     if (!wave_wait(&A.w.tflag[tidx(A, m, s)], A.w) || !wave_wait(&A.w.tflag[tidx(A, m - 1, s)], A.w)) {
@@ -213,25 +232,28 @@ __device__ __attribute__((noinline)) void task_pre(const Args& A_, int64_t m, ld
 
 // ---------------------------------------------------------------- spine
 
+template <typename F>
 struct SpineLds {
-  lds_d* diag;    // staged diagonal tile (column-major, LP)
-  lds_d* acco;    // staged tile (C+1, C)
-  lds_d* accd;    // next diagonal tile before its last update
-  lds_d* lcur;    // L(C+1, C)
-  lds_d* lprev;   // L(C, C-1)
-  lds_d* linvt;   // L(C,C)^{-T}, row-major, row pitch LP
-  lds_d* lcc;     // L(C,C) (column-major, LP)
+  lds_t<F>* diag;    // staged diagonal tile (column-major, LP)
+  lds_t<F>* acco;    // staged tile (C+1, C)
+  lds_t<F>* accd;    // next diagonal tile before its last update
+  lds_t<F>* lcur;    // L(C+1, C)
+  lds_t<F>* lprev;   // L(C, C-1)
+  lds_t<F>* linvt;   // L(C,C)^{-T}, row-major, row pitch LP
+  lds_t<F>* lcc;     // L(C,C) (column-major, LP)
 };
 
-__device__ __attribute__((noinline)) void spine_sweep(const Args& A_, int64_t C, const SpineLds& S_, lds_i* s_fail) {
-  const Args A = A_;
-  const SpineLds S = S_;
+template <typename F>
+__device__ __attribute__((noinline)) void spine_sweep(const Args<F>& A_, int64_t C, const SpineLds<F>& S_,
+                                                      lds_i* s_fail) {
+  const Args<F> A = A_;
+  const SpineLds<F> S = S_;
   const int lane = lane_id();
-  const Band& a = A.a;
-  double row[T];
+  const BandT<F>& a = A.a;
+  F row[T];
 #pragma unroll
-  for (int c = 0; c < T; ++c) row[c] = lane < T ? S.diag[c * LP + lane] : ((lane - T) == c ? 1.0 : 0.0);
-  const int fail = sweep_ldlt(row, nullptr);
+  for (int c = 0; c < T; ++c) row[c] = lane < T ? S.diag[c * LP + lane] : ((lane - T) == c ? F(1) : F(0));
+  const int fail = sweep_ldlt(row);
   if (fail >= 0) {
     if (lane == 0) {
       *s_fail = fail;
@@ -253,34 +275,35 @@ __device__ __attribute__((noinline)) void spine_sweep(const Args& A_, int64_t C,
 // One wave copies the spine's results of step C from LDS to global memory with
 // coalesced stores: L(C,C) (lower triangle), L(C,C)^{-T} (row-major, for the
 // helpers' trsm) and, if `off`, L(C+1, C) from `lcur`.  Does not wait for them.
-__device__ __attribute__((noinline)) void spine_publish(const Args& A_, int64_t C, const SpineLds& S_, const lds_d* lcur,
-                                                        bool off) {
-  const Args A = A_;
-  const SpineLds S = S_;
-  const Band& a = A.a;
+template <typename F>
+__device__ __attribute__((noinline)) void spine_publish(const Args<F>& A_, int64_t C, const SpineLds<F>& S_,
+                                                        const lds_t<F>* lcur, bool off) {
+  const Args<F> A = A_;
+  const SpineLds<F> S = S_;
+  const BandT<F>& a = A.a;
   const int lane = lane_id();
   const int r = lane & 31;
-  glb_d* lt = A.w.linvt + C * T * T;
+  glb_t<F>* lt = A.w.linvt + C * T * T;
   // all LDS reads first, then the stores (a store waiting on its own read
   // would serialise the LDS latency)
-  double vl[T / 2], vt[T / 2], vo[T / 2];
+  F vl[T / 2], vt[T / 2], vo[T / 2];
 #pragma unroll
   for (int p = 0; p < T / 2; ++p) {
     const int c = 2 * p + (lane >> 5);
     const int e = 64 * p + lane;
     vl[p] = S.lcc[c * LP + r];
     vt[p] = S.linvt[(e / T) * LP + (e % T)];
-    vo[p] = off ? lcur[c * LP + r] : 0.0;
+    vo[p] = off ? lcur[c * LP + r] : F(0);
   }
   // lane (r, h) stores column 2p + h of rows r of tiles (C, C) and (C+1, C)
-  const Run rd = band_run(a, C * T + r, C * T + (lane >> 5), 2);
+  const RunT<F> rd = band_run(a, C * T + r, C * T + (lane >> 5), 2);
 #pragma unroll
   for (int p = 0; p < T / 2; ++p)
     if (rd.in(p)) astore(rd.at(p), vl[p]);
 #pragma unroll
   for (int p = 0; p < T / 2; ++p) astore(lt + 64 * p + lane, vt[p]);
   if (off) {
-    const Run ro = band_run(a, (C + 1) * T + r, C * T + (lane >> 5), 2);
+    const RunT<F> ro = band_run(a, (C + 1) * T + r, C * T + (lane >> 5), 2);
 #pragma unroll
     for (int p = 0; p < T / 2; ++p)
       if (ro.in(p)) astore(ro.at(p), vo[p]);
@@ -292,25 +315,27 @@ __device__ __attribute__((noinline)) void spine_publish(const Args& A_, int64_t 
 // b = wave-1, wave+2, wave+5.  The term s = C-1 uses X = L(m, C-1) for both
 // tiles, Y = L(C, C-1) (staged in LDS) for (m, C) and Y = L(m, C-1) for (m, m);
 // every global load is issued before the first MFMA.
-__device__ __attribute__((noinline)) void spine_prepare(const Args& A_, int64_t C, const SpineLds& S_, lds_i* s_fail) {
-  const Args A = A_;
-  const SpineLds S = S_;
+template <typename F>
+__device__ __attribute__((noinline)) void spine_prepare(const Args<F>& A_, int64_t C, const SpineLds<F>& S_,
+                                                        lds_i* s_fail) {
+  const Args<F> A = A_;
+  const SpineLds<F> S = S_;
   const int wave = wave_id();
   const int lane = lane_id();
   const int64_t m = C + 1;
   const bool have_pre = A.K >= 3 && m >= 3;
-  const glb_d* po = A.w.pre + m * 2 * T * T;
-  const glb_d* pd = po + T * T;
+  const glb_t<F>* po = A.w.pre + m * 2 * T * T;
+  const glb_t<F>* pd = po + T * T;
   if (have_pre && !wave_wait(&A.w.hflag[m], A.w)) { if (lane == 0) *s_fail = -2; return; }
   // term s = C-1 needs L(m, C-1) (a helper tile) and L(C, C-1) (S.lprev)
   const bool t1 = C >= 1 && A.K >= 2;
   if (t1 && !wave_wait(&A.w.tflag[tidx(A, m, C - 1)], A.w)) { if (lane == 0) *s_fail = -2; return; }
-  d4 acc[3];
-  double x0[T / 4], x1[T / 4];  // fragments of L(m, C-1), rows 0-15 and 16-31
+  v4_t<F> acc[3];
+  F x0[T / 4], x1[T / 4];  // fragments of L(m, C-1), rows 0-15 and 16-31
 #pragma unroll
   for (int u = 0; u < 3; ++u) {
     const int b = wave - 1 + 3 * u;
-    acc[u] = d4{0, 0, 0, 0};
+    acc[u] = v4_t<F>{0, 0, 0, 0};
     if (b < 4) {
       const int bi = b & 1, bj = b >> 1;
       acc[u] = have_pre ? wblk_load(po, bi, bj) : ablk_load(A.a, m, C, bi, bj);
@@ -321,8 +346,8 @@ __device__ __attribute__((noinline)) void spine_prepare(const Args& A_, int64_t 
   }
   if (t1) {
     const int64_t j0 = (C - 1) * T + (lane >> 4);
-    const Run r0 = band_run(A.a, m * T + (lane & 15), j0, 4);
-    const Run r1 = band_run(A.a, m * T + 16 + (lane & 15), j0, 4);
+    const RunT<F> r0 = band_run(A.a, m * T + (lane & 15), j0, 4);
+    const RunT<F> r1 = band_run(A.a, m * T + 16 + (lane & 15), j0, 4);
 #pragma unroll
     for (int q = 0; q < T / 4; ++q) {
       x0[q] = r0.ald(q);
@@ -351,10 +376,11 @@ __device__ __attribute__((noinline)) void spine_prepare(const Args& A_, int64_t 
   }
 }
 
-__device__ void spine(const Args& A, lds_d* base, lds_i* s_fail) {
+template <typename F>
+__device__ void spine(const Args<F>& A, lds_t<F>* base, lds_i* s_fail) {
   const int wave = wave_id();
-  const Band& a = A.a;
-  SpineLds S;
+  const BandT<F>& a = A.a;
+  SpineLds<F> S;
   S.diag = base;
   S.acco = S.diag + T * LP;
   S.accd = S.acco + T * LP;
@@ -368,7 +394,7 @@ __device__ void spine(const Args& A, lds_d* base, lds_i* s_fail) {
     const int bi = (wave >= 2), bj = (wave == 3);
     blk_to_lds(S.diag, bi, bj, ablk_load(a, 0, 0, bi, bj));
   } else {
-    blk_to_lds(S.diag, 0, 1, d4{0, 0, 0, 0});
+    blk_to_lds(S.diag, 0, 1, v4_t<F>{0, 0, 0, 0});
   }
   __syncthreads();
   for (int64_t C = 0; C < A.NB; ++C) {
@@ -405,14 +431,12 @@ __device__ void spine(const Args& A, lds_d* base, lds_i* s_fail) {
       spine_publish(A, C, S, S.lcur, A.K >= 1);
     } else {
       const int bi = (wave >= 2), bj = (wave == 3);
-      d4 acc = {0, 0, 0, 0};
-#pragma unroll
-      for (int r = 0; r < 4; ++r) acc[r] = S.accd[(16 * bj + 4 * r + (lane_id() >> 4)) * LP + 16 * bi + (lane_id() & 15)];
-      if (A.K >= 1) acc = blk_gemm_lds(S.lcur, S.lcur, bi, bj, acc);
-      blk_to_lds(S.diag, bi, bj, acc);
-      if (wave == 0) blk_to_lds(S.diag, 0, 1, d4{0, 0, 0, 0});
+      v4_t<F> acc = blk_from_lds<F>(S.accd, bi, bj);
+      if (A.K >= 1) acc = blk_gemm_lds<F>(S.lcur, S.lcur, bi, bj, acc);
+      blk_to_lds<F>(S.diag, bi, bj, acc);
+      if (wave == 0) blk_to_lds<F>(S.diag, 0, 1, v4_t<F>{0, 0, 0, 0});
     }
-    lds_d* t = S.lprev; S.lprev = S.lcur; S.lcur = t;
+    lds_t<F>* t = S.lprev; S.lprev = S.lcur; S.lcur = t;
     __syncthreads();
   }
 }
@@ -424,7 +448,8 @@ __host__ __device__ __forceinline__ unsigned tickets_per_column(int K) {
   return K >= 2 ? (unsigned)(K - 1) + (K >= 3 ? 1u : 0u) : 0u;
 }
 
-__device__ __forceinline__ void decode(const Args& A, unsigned t, int& kind, int64_t& R, int64_t& C) {
+template <typename F>
+__device__ __forceinline__ void decode(const Args<F>& A, unsigned t, int& kind, int64_t& R, int64_t& C) {
   const unsigned per = tickets_per_column(A.K);
   const unsigned u = t - 1;
   C = u / per;
@@ -438,8 +463,9 @@ __device__ __forceinline__ void decode(const Args& A, unsigned t, int& kind, int
   }
 }
 
-__global__ void __launch_bounds__(NT, 2) factor2_kernel(Args A) {
-  __shared__ double lds[7 * T * LP];
+template <typename F>
+__global__ void __launch_bounds__(NT, 2) factor2_kernel(Args<F> A) {
+  __shared__ F lds[7 * T * LP];
   __shared__ int s_ticket, s_ok, s_abort;
   for (;;) {
     if (threadIdx.x == 0) {
@@ -454,13 +480,13 @@ __global__ void __launch_bounds__(NT, 2) factor2_kernel(Args A) {
     __syncthreads();
     if (t >= A.ntickets || stop) break;
     if (t == 0) {
-      spine(A, (lds_d*)lds, (lds_i*)&s_ok);
+      spine<F>(A, (lds_t<F>*)lds, (lds_i*)&s_ok);
     } else {
       int kind;
       int64_t R, C;
       decode(A, t, kind, R, C);
       if (R < A.NB) {
-        if (kind == 1) task_off(A, R, C, (lds_d*)lds, (lds_i*)&s_ok);
+        if (kind == 1) task_off<F>(A, R, C, (lds_t<F>*)lds, (lds_i*)&s_ok);
         else task_pre(A, R, (lds_i*)&s_ok);
       }
     }
@@ -482,23 +508,27 @@ __global__ void factor2_finish(const glb_i* abort_flag, const unsigned long long
 
 }  // namespace bandchol_f2
 
-// Workspace bytes for n, k (K = sub-diagonal tile count).
-size_t bandchol_factor2_workspace(int64_t n, int64_t K) {
+// Workspace bytes for n, K (sub-diagonal tile count) and the element size.
+static size_t factor2_workspace(int64_t n, int64_t K, size_t elem) {
   using namespace bandchol_f2;
   const int64_t NB = (n + T - 1) / T;
   const size_t flags = sizeof(int) * (size_t)(NB * (K + 1) + NB);
-  return 256 + ((flags + 255) & ~(size_t)255) + sizeof(double) * (size_t)NB * T * T * 3;
+  return 256 + ((flags + 255) & ~(size_t)255) + elem * (size_t)NB * T * T * 3;
 }
 
-hipError_t bandchol_factor2_launch(int64_t n, int64_t k, double* ab, int64_t ldab, int64_t* d_info, void* ws,
-                                   int grid_max, hipStream_t st) {
+size_t bandchol_factor2_workspace(int64_t n, int64_t K) { return factor2_workspace(n, K, sizeof(double)); }
+size_t bandchol_factor2_workspace_f32(int64_t n, int64_t K) { return factor2_workspace(n, K, sizeof(float)); }
+
+template <typename F>
+static hipError_t factor2_launch(int64_t n, int64_t k, F* ab, int64_t ldab, int64_t* d_info, void* ws, int grid_max,
+                                 hipStream_t st) {
   using namespace bandchol_f2;
   const int NB = (int)((n + T - 1) / T);
   int K = (int)((k + T - 1) / T);
   if (K > NB - 1) K = NB - 1 > 0 ? NB - 1 : 0;
   char* base = (char*)ws;
-  Args A;
-  A.a = Band{(glb_d*)ab, n, k, ldab};
+  Args<F> A;
+  A.a = BandT<F>{(glb_t<F>*)ab, n, k, ldab};
   A.NB = NB;
   A.K = K;
   A.w.queue = (unsigned*)base;
@@ -507,7 +537,7 @@ hipError_t bandchol_factor2_launch(int64_t n, int64_t k, double* ab, int64_t lda
   A.w.tflag = (glb_i*)(base + 256);
   A.w.hflag = A.w.tflag + (size_t)NB * (K + 1);
   const size_t flags = sizeof(int) * (size_t)(NB * (K + 1) + NB);
-  A.w.linvt = (glb_d*)(base + 256 + ((flags + 255) & ~(size_t)255));
+  A.w.linvt = (glb_t<F>*)(base + 256 + ((flags + 255) & ~(size_t)255));
   A.w.pre = A.w.linvt + (size_t)NB * T * T;
   A.ntickets = 1 + tickets_per_column(K) * (unsigned)NB;
   const int64_t nflags = (int64_t)NB * (K + 1) + NB;
@@ -515,7 +545,17 @@ hipError_t bandchol_factor2_launch(int64_t n, int64_t k, double* ab, int64_t lda
       A.w.tflag, nflags, A.w.queue, A.w.abort_flag, A.w.first_fail);
   int grid = grid_max;
   if ((unsigned)grid > A.ntickets) grid = (int)A.ntickets;
-  factor2_kernel<<<grid, NT, 0, st>>>(A);
+  factor2_kernel<F><<<grid, NT, 0, st>>>(A);
   factor2_finish<<<1, 1, 0, st>>>(A.w.abort_flag, A.w.first_fail, d_info);
   return hipGetLastError();
+}
+
+hipError_t bandchol_factor2_launch(int64_t n, int64_t k, double* ab, int64_t ldab, int64_t* d_info, void* ws,
+                                   int grid_max, hipStream_t st) {
+  return factor2_launch<double>(n, k, ab, ldab, d_info, ws, grid_max, st);
+}
+
+hipError_t bandchol_factor2_launch_f32(int64_t n, int64_t k, float* ab, int64_t ldab, int64_t* d_info, void* ws,
+                                       int grid_max, hipStream_t st) {
+  return factor2_launch<float>(n, k, ab, ldab, d_info, ws, grid_max, st);
 }

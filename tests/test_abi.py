@@ -84,3 +84,25 @@ def test_batch_bad_arguments_rejected_on_host():
     assert lib.bandchol_batch_solve(None, -1, None) == -1
     assert lib.bandchol_batch_solve(None, 1, None) == -3
     lib.bandchol_batch_destroy(None)          # no-op
+
+
+def test_f32_and_mixed_bad_arguments_rejected_on_host():
+    lib = bc.load()
+    assert lib.bandchol_factor_f32(-1, 2, None, 3, 8, None) == -1
+    assert lib.bandchol_factor_f32(5, -1, None, 3, 8, None) == -2
+    assert lib.bandchol_factor_f32(5, 2, None, 3, 8, None) == -3
+    assert lib.bandchol_factor_f32(5, 2, 8, 2, 8, None) == -4
+    assert lib.bandchol_factor_f32(5, 2, 8, 3, None, None) == -5
+    m = lib.bandchol_mixed_solve
+    assert m(-1, 2, 1, 8, 3, 8, 5, 8, 5, None, None) == -1
+    assert m(5, -2, 1, 8, 3, 8, 5, 8, 5, None, None) == -2
+    assert m(5, 2, -1, 8, 3, 8, 5, 8, 5, None, None) == -3
+    assert m(5, 2, 1, None, 3, 8, 5, 8, 5, None, None) == -4
+    assert m(5, 2, 1, 8, 2, 8, 5, 8, 5, None, None) == -5
+    assert m(5, 2, 1, 8, 3, None, 5, 8, 5, None, None) == -6
+    assert m(5, 2, 1, 8, 3, 8, 4, 8, 5, None, None) == -7
+    assert m(5, 2, 1, 8, 3, 8, 5, None, 5, None, None) == -8
+    assert m(5, 2, 1, 8, 3, 8, 5, 8, 4, None, None) == -9
+    it, fb = ctypes.c_int64(7), ctypes.c_int64(7)
+    assert m(0, 2, 1, None, 3, None, 1, None, 1, ctypes.byref(it), ctypes.byref(fb)) == 0
+    assert it.value == 0 and fb.value == 0
