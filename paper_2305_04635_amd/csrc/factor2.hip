@@ -241,6 +241,8 @@ struct SpineLds {
   lds_t<F>* lprev;   // L(C, C-1)
   lds_t<F>* linvt;   // L(C,C)^{-T}, row-major, row pitch LP
   lds_t<F>* lcc;     // L(C,C) (column-major, LP)
+  lds_t<F>* linvt_prev;   // the same two of the previous step, being published
+  lds_t<F>* lcc_prev;
 };
 
 template <typename F>
@@ -272,41 +274,45 @@ __device__ __attribute__((noinline)) void spine_sweep(const Args<F>& A_, int64_t
   }
 }
 
-// One wave copies the spine's results of step C from LDS to global memory with
-// coalesced stores: L(C,C) (lower triangle), L(C,C)^{-T} (row-major, for the
-// helpers' trsm) and, if `off`, L(C+1, C) from `lcur`.  Does not wait for them.
+// Waves 1-3 copy the spine's results of step C from LDS to global memory with
+// coalesced stores, one part each: wave 1 L(C,C) (lower triangle, from `lcc`),
+// wave 2 L(C,C)^{-T} (row-major, for the helpers' trsm, from `linvt`), wave 3
+// L(C+1, C) from `lcur` (if `off`).  Does not wait for them.
 template <typename F>
-__device__ __attribute__((noinline)) void spine_publish(const Args<F>& A_, int64_t C, const SpineLds<F>& S_,
-                                                        const lds_t<F>* lcur, bool off) {
+__device__ __attribute__((noinline)) void spine_publish(const Args<F>& A_, int64_t C, const lds_t<F>* lcc,
+                                                        const lds_t<F>* linvt, const lds_t<F>* lcur, bool off,
+                                                        int part) {
   const Args<F> A = A_;
-  const SpineLds<F> S = S_;
   const BandT<F>& a = A.a;
   const int lane = lane_id();
   const int r = lane & 31;
-  glb_t<F>* lt = A.w.linvt + C * T * T;
   // all LDS reads first, then the stores (a store waiting on its own read
   // would serialise the LDS latency)
-  F vl[T / 2], vt[T / 2], vo[T / 2];
+  F v[T / 2];
+  if (part == 1) {
 #pragma unroll
-  for (int p = 0; p < T / 2; ++p) {
-    const int c = 2 * p + (lane >> 5);
-    const int e = 64 * p + lane;
-    vl[p] = S.lcc[c * LP + r];
-    vt[p] = S.linvt[(e / T) * LP + (e % T)];
-    vo[p] = off ? lcur[c * LP + r] : F(0);
-  }
-  // lane (r, h) stores column 2p + h of rows r of tiles (C, C) and (C+1, C)
-  const RunT<F> rd = band_run(a, C * T + r, C * T + (lane >> 5), 2);
+    for (int p = 0; p < T / 2; ++p) v[p] = lcc[(2 * p + (lane >> 5)) * LP + r];
+    // lane (r, h) stores column 2p + h of row r
+    const RunT<F> rd = band_run(a, C * T + r, C * T + (lane >> 5), 2);
 #pragma unroll
-  for (int p = 0; p < T / 2; ++p)
-    if (rd.in(p)) astore(rd.at(p), vl[p]);
+    for (int p = 0; p < T / 2; ++p)
+      if (rd.in(p)) astore(rd.at(p), v[p]);
+  } else if (part == 2) {
+    glb_t<F>* lt = A.w.linvt + C * T * T;
 #pragma unroll
-  for (int p = 0; p < T / 2; ++p) astore(lt + 64 * p + lane, vt[p]);
-  if (off) {
+    for (int p = 0; p < T / 2; ++p) {
+      const int e = 64 * p + lane;
+      v[p] = linvt[(e / T) * LP + (e % T)];
+    }
+#pragma unroll
+    for (int p = 0; p < T / 2; ++p) astore(lt + 64 * p + lane, v[p]);
+  } else if (part == 3 && off) {
+#pragma unroll
+    for (int p = 0; p < T / 2; ++p) v[p] = lcur[(2 * p + (lane >> 5)) * LP + r];
     const RunT<F> ro = band_run(a, (C + 1) * T + r, C * T + (lane >> 5), 2);
 #pragma unroll
     for (int p = 0; p < T / 2; ++p)
-      if (ro.in(p)) astore(ro.at(p), vo[p]);
+      if (ro.in(p)) astore(ro.at(p), v[p]);
   }
 }
 
@@ -377,7 +383,7 @@ __device__ __attribute__((noinline)) void spine_prepare(const Args<F>& A_, int64
 }
 
 template <typename F>
-__device__ void spine(const Args<F>& A, lds_t<F>* base, lds_i* s_fail) {
+__device__ void spine(const Args<F>& A, lds_t<F>* base, lds_i* s_fail, lds_i* s_pub) {
   const int wave = wave_id();
   const BandT<F>& a = A.a;
   SpineLds<F> S;
@@ -388,7 +394,12 @@ __device__ void spine(const Args<F>& A, lds_t<F>* base, lds_i* s_fail) {
   S.lprev = S.lcur + T * LP;
   S.linvt = S.lprev + T * LP;
   S.lcc = S.linvt + T * LP;
-  if (threadIdx.x == 0) *s_fail = -1;
+  S.linvt_prev = S.lcc + T * LP;
+  S.lcc_prev = S.linvt_prev + T * LP;
+  if (threadIdx.x == 0) {
+    *s_fail = -1;
+    *s_pub = 0;
+  }
   // stage tile (0,0)
   if (wave >= 1) {
     const int bi = (wave >= 2), bj = (wave == 3);
@@ -399,12 +410,19 @@ __device__ void spine(const Args<F>& A, lds_t<F>* base, lds_i* s_fail) {
   __syncthreads();
   for (int64_t C = 0; C < A.NB; ++C) {
     const bool next = C + 1 < A.NB;
-    // results of step C-1 published by wave 1 in its phase C: drain, then flag
-    if (wave == 1 && C >= 1) {
+    // waves 1-3 publish step C-1 (its L(C-1,C-1) and inverse sit in the
+    // previous-step buffers, L(C,C-1) in lprev) while wave 0 already sweeps
+    // step C; each drains its own stores and counts in; the third raises the
+    // flags (the prepare below waits, through a helper task, on them)
+    if (wave >= 1 && C >= 1) {
+      spine_publish(A, C - 1, S.lcc_prev, S.linvt_prev, S.lprev, A.K >= 1, wave);
       wait_vmem();
       if (lane_id() == 0) {
-        raise_flag(&A.w.tflag[tidx(A, C - 1, C - 1)]);
-        if (A.K >= 1) raise_flag(&A.w.tflag[tidx(A, C, C - 1)]);
+        const int before = __hip_atomic_fetch_add(s_pub, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (before == 3 * (int)C - 1) {
+          raise_flag(&A.w.tflag[tidx(A, C - 1, C - 1)]);
+          if (A.K >= 1) raise_flag(&A.w.tflag[tidx(A, C, C - 1)]);
+        }
       }
     }
     // phase A
@@ -417,7 +435,7 @@ __device__ void spine(const Args<F>& A, lds_t<F>* base, lds_i* s_fail) {
     __syncthreads();
     if (*s_fail != -1) return;
     if (!next) {
-      if (wave == 1) spine_publish(A, C, S, S.lcur, false);
+      if (wave >= 1) spine_publish(A, C, S.lcc, S.linvt, S.lcur, false, wave);
       return;
     }
     // phase B: L(C+1, C) = acco * L(C,C)^{-T}, into LDS
@@ -426,10 +444,8 @@ __device__ void spine(const Args<F>& A, lds_t<F>* base, lds_i* s_fail) {
       blk_to_lds(S.lcur, bi, bj, blk_trsm_lds(S.acco, S.linvt, bi, bj, LP));
     }
     __syncthreads();
-    // phase C: next diagonal tile (waves 0, 2, 3); wave 1 publishes step C
-    if (wave == 1) {
-      spine_publish(A, C, S, S.lcur, A.K >= 1);
-    } else {
+    // phase C: next diagonal tile (blocks (0,0), (1,0), (1,1) on waves 0, 2, 3)
+    if (wave != 1) {
       const int bi = (wave >= 2), bj = (wave == 3);
       v4_t<F> acc = blk_from_lds<F>(S.accd, bi, bj);
       if (A.K >= 1) acc = blk_gemm_lds<F>(S.lcur, S.lcur, bi, bj, acc);
@@ -437,6 +453,8 @@ __device__ void spine(const Args<F>& A, lds_t<F>* base, lds_i* s_fail) {
       if (wave == 0) blk_to_lds<F>(S.diag, 0, 1, v4_t<F>{0, 0, 0, 0});
     }
     lds_t<F>* t = S.lprev; S.lprev = S.lcur; S.lcur = t;
+    t = S.lcc_prev; S.lcc_prev = S.lcc; S.lcc = t;
+    t = S.linvt_prev; S.linvt_prev = S.linvt; S.linvt = t;
     __syncthreads();
   }
 }
@@ -465,8 +483,8 @@ __device__ __forceinline__ void decode(const Args<F>& A, unsigned t, int& kind, 
 
 template <typename F>
 __global__ void __launch_bounds__(NT, 2) factor2_kernel(Args<F> A) {
-  __shared__ F lds[7 * T * LP];
-  __shared__ int s_ticket, s_ok, s_abort;
+  __shared__ F lds[9 * T * LP];
+  __shared__ int s_ticket, s_ok, s_abort, s_pub;
   for (;;) {
     if (threadIdx.x == 0) {
       s_ticket = (int)atomicAdd(A.w.queue, 1u);
@@ -480,7 +498,7 @@ __global__ void __launch_bounds__(NT, 2) factor2_kernel(Args<F> A) {
     __syncthreads();
     if (t >= A.ntickets || stop) break;
     if (t == 0) {
-      spine<F>(A, (lds_t<F>*)lds, (lds_i*)&s_ok);
+      spine<F>(A, (lds_t<F>*)lds, (lds_i*)&s_ok, (lds_i*)&s_pub);
     } else {
       int kind;
       int64_t R, C;
