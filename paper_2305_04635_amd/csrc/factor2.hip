@@ -317,8 +317,9 @@ __device__ __attribute__((noinline)) void spine_publish(const Args<F>& A_, int64
 }
 
 // waves 1-3: tiles (C+1, C) and (C+1, C+1) with everything but the critical
-// update.  The 7 lower blocks (4 of (m, C), 3 of (m, m)) go to waves 1-3 as
-// b = wave-1, wave+2, wave+5.  The term s = C-1 uses X = L(m, C-1) for both
+// update.  The 7 lower blocks (4 of (m, C), 3 of (m, m)) go to waves 2 and 3
+// three each (b = 0, 2, 4 and 1, 3, 5) and to wave 1 one (b = 6), since wave 1
+// also publishes a third of the previous step.  The term s = C-1 uses X = L(m, C-1) for both
 // tiles, Y = L(C, C-1) (staged in LDS) for (m, C) and Y = L(m, C-1) for (m, m);
 // every global load is issued before the first MFMA.
 template <typename F>
@@ -340,7 +341,7 @@ __device__ __attribute__((noinline)) void spine_prepare(const Args<F>& A_, int64
   F x0[T / 4], x1[T / 4];  // fragments of L(m, C-1), rows 0-15 and 16-31
 #pragma unroll
   for (int u = 0; u < 3; ++u) {
-    const int b = wave - 1 + 3 * u;
+    const int b = wave == 1 ? (u == 0 ? 6 : 7) : wave - 2 + 2 * u;
     acc[u] = v4_t<F>{0, 0, 0, 0};
     if (b < 4) {
       const int bi = b & 1, bj = b >> 1;
@@ -362,7 +363,7 @@ __device__ __attribute__((noinline)) void spine_prepare(const Args<F>& A_, int64
   }
 #pragma unroll
   for (int u = 0; u < 3; ++u) {
-    const int b = wave - 1 + 3 * u;
+    const int b = wave == 1 ? (u == 0 ? 6 : 7) : wave - 2 + 2 * u;
     if (b < 4) {
       const int bi = b & 1, bj = b >> 1;
       if (t1) {
