@@ -31,7 +31,7 @@
 #include "mixed.h"
 #include "walk.h"
 
-size_t bandchol_solve_workspace(int64_t n);
+size_t bandchol_solve_workspace(int64_t n, int64_t k);
 size_t bandchol_factor2_workspace(int64_t n, int64_t K);
 size_t bandchol_factor2_workspace_f32(int64_t n, int64_t K);
 hipError_t bandchol_factor2_launch_f32(int64_t n, int64_t k, float* ab, int64_t ldab, int64_t* d_info, void* ws,
@@ -255,7 +255,7 @@ int64_t solve_async_impl(int64_t n, int64_t k, int64_t nrhs, const double* ab, i
   if (n == 0 || nrhs == 0) return 0;
   const int64_t kk = k < n - 1 ? k : n - 1;
   hipError_t e;
-  void* ws = workspace(bandchol_solve_workspace(n), &e);
+  void* ws = workspace(bandchol_solve_workspace(n, kk), &e);
   if (!ws) { set_err("workspace", e); return BANDCHOL_EHIP; }
   e = bandchol_solve_launch(n, kk, nrhs, ab, ldab, b, ldb, ws, num_cus(), st);
   if (e != hipSuccess) { set_err("solve launch", e); return BANDCHOL_EHIP; }
@@ -571,7 +571,7 @@ int64_t bandchol_batch_create(int64_t batch, const int64_t* n, const int64_t* k,
     } else {
       p->wide.push_back(w);
       p->wide_id.push_back(i);
-      wide_ws = std::max(wide_ws, std::max(bandchol_factor2_workspace(n[i], K), bandchol_solve_workspace(n[i])));
+      wide_ws = std::max(wide_ws, std::max(bandchol_factor2_workspace(n[i], K), bandchol_solve_workspace(n[i], kk)));
     }
   }
   const int nw = (int)p->walk.size();
