@@ -1,11 +1,23 @@
 // Band solves with the factor: forward L Y = B, then back L^T X = Y (gfx950, FP64).
 //
-// Both directions walk the band in T-row blocks and form each block from the
-// previous (or next) KS blocks.  One workgroup (the spine, whoever takes ticket
-// 0) carries the dependency chain: for block B it applies the contributions of
-// the nearest ST blocks itself, then multiplies by the inverse of the diagonal
-// tile.  Helper workgroups take the other tickets and pre-accumulate, for each
-// block, the contributions of all blocks further away.
+// Both directions walk the band in blocks of SB = 64 rows (two tiles) and form
+// each block from the previous (or next) KS blocks.  One workgroup (the
+// spine, whoever takes ticket 0) carries the dependency chain: for block B it
+// applies the contributions of the nearest ST blocks itself, then solves with
+// the diagonal block.  Helper workgroups take the other tickets and
+// pre-accumulate, for each block, the contributions of all blocks further
+// away.  A step of the chain costs about the same whatever its width (its
+// loads are issued ahead, its arithmetic is short), so blocks of two tiles
+// halve the number of steps.
+//
+// The diagonal block [A 0; C D] (A, C, D tiles) is solved by block
+// substitution with precomputed operators, not with the inverse of the whole
+// block: forward y1 = A^{-1} t1 and u2 = t2 - (C A^{-1}) t1, then
+// y2 = D^{-1} u2; back x2 = D^{-T} t2 and u1 = t1 - (D^{-1} C)^T t2, then
+// x1 = A^{-T} u1.  The subtraction comes before the last inverse is applied,
+// as in a substitution tile by tile; multiplying by the inverse of the whole
+// block would add products of both tile inverses to nearly cancelling terms
+// and lose accuracy on ill-conditioned blocks.
 //
 // Publication without flags: every block of the result and every helper sum is
 // written, by relaxed agent-scope atomic stores, into a buffer filled
@@ -16,7 +28,7 @@
 // sum is ready for the spine one store latency after it is formed.
 //
 // The spine's operands that do not depend on the chain (its blocks of L, the
-// inverse of the diagonal tile, the right-hand side and the helper sum) are
+// inverse of the diagonal block, the right-hand side and the helper sum) are
 // loaded two steps ahead, into two register stages used alternately, so that
 // a step costs its arithmetic and two barriers, not memory latencies.
 #include <stdint.h>
@@ -30,23 +42,24 @@ using namespace bandchol;
 typedef double d2 __attribute__((ext_vector_type(2)));
 typedef glb_t<d2> glb_d2;
 
-constexpr int NT = 256;
+constexpr int SB = 64;               // rows per block
+constexpr int NT = 512;              // threads: (i, p) = (tid / 8, tid % 8), row i, columns 8p .. 8p+7
+constexpr int QP = 8;                // columns per thread
 constexpr int RHS_MAX = 8;           // right-hand sides per launch (thread p completes r = p)
-constexpr int G = 4;                 // blocks a helper loads at once
-constexpr int HR = 2;                // right-hand sides per helper pass
-constexpr int ST_MAX = 8;            // most blocks the spine applies itself
+constexpr int G = 2;                 // blocks a helper loads at once
+constexpr int ST_MAX = 2;            // most blocks the spine applies itself
 constexpr long long SPIN_LIMIT = 1LL << 24;
 constexpr long long UNSET = 0x7FF4DEADBEEF0001LL;   // a signalling NaN
 
 struct SolveArgs {
   Band a;
-  int NB, KS, nrhs;
-  int64_t NBT;            // NB * T, the length of a published column
-  const glb_d* ops;       // the spine's operands, per block (layout below)
+  int NB, KS, nrhs;       // blocks, blocks of bandwidth, right-hand sides
+  int64_t NBT;            // NB * SB, the length of a published column
+  const glb_d* ops;       // the spine's operands, per block (layout at chunk_len)
   const glb_d* in;        // forward: b; back: the forward result
   int64_t ldin;
   glb_d* pub;             // this direction's result, published (column length NBT)
-  glb_d* z;               // helper sums, published: (B * nrhs + r) * T + i
+  glb_d* z;               // helper sums, published: (B * nrhs + r) * SB + i
   glb_d* out;             // back: b, receives the solution; forward: unused
   int64_t ldout;
   unsigned* queue;        // ticket counter
@@ -109,27 +122,46 @@ __device__ __forceinline__ double red8(double s) {
   return s;
 }
 
-// Operands of one spine step, loaded ahead.  Thread (i, p) = (tid / 8, tid % 8)
-// holds, for the step's block B and its neighbours N = B -+ d (d = 1 .. ST):
-//   forward: lf[d-1][q] = L(B T + i, N T + 4p + q), df[q] = L(B,B)^{-1}(i, 4p + q)
-//   back:    lf[d-1][q] = L(N T + 4p + q, B T + i), df[q] = L(B,B)^{-1}(4p + q, i)
-// (zero outside the band and past either end), and the right-hand side and
-// helper sum of row i for r = p.
+// sum_q x[q] y[q] over 8 terms, as two chains of 4
+__device__ __forceinline__ double dot8(const double (&x)[QP], const lds_d* y) {
+  double a0 = x[0] * y[0], a1 = x[4] * y[4];
+  a0 = fma(x[1], y[1], a0);
+  a1 = fma(x[5], y[5], a1);
+  a0 = fma(x[2], y[2], a0);
+  a1 = fma(x[6], y[6], a1);
+  a0 = fma(x[3], y[3], a0);
+  a1 = fma(x[7], y[7], a1);
+  return a0 + a1;
+}
+
+// sum_q x[o + q] y[q] over 4 terms
+__device__ __forceinline__ double dot4(const double (&x)[QP], int o, const lds_d* y) {
+  return fma(x[o + 3], y[3], fma(x[o + 2], y[2], fma(x[o + 1], y[1], x[o] * y[0])));
+}
+
+// Operands of one spine step, loaded ahead.  Thread (i, p) holds, for the
+// step's block B and its neighbours N = B -+ d (d = 1 .. ST):
+//   forward: lf[d-1][q] = L(B SB + i, N SB + 8p + q)
+//   back:    lf[d-1][q] = L(N SB + 8p + q, B SB + i)
+// (zero outside the band and past either end); in df, row i, columns
+// 4p .. 4p+3 of the two operators of the diagonal block (see block_operators):
+// df[0..3] of P (64 x 32), df[4..7] of R (32 x 32, zero in the rows that P
+// completes); and the right-hand side and helper sum of row i for r = p.
 template <int ST>
 struct Stage {
-  double lf[ST][4];
-  double df[4];
+  double lf[ST][QP];
+  double df[QP];
   double bv, zv;
 };
 
-// The operand buffer holds, per block B, the ST tiles of L and the inverse of
-// the diagonal tile that the spine's step on B reads, zero-padded, in the
-// order of the threads: tile t, elements q = 2h and 2h+1 of thread tid at
-// ((t * 2 + h) * NT + tid) * 2.  Every load of a step is then a coalesced
+// The operand buffer holds, per block B, the ST blocks of L and the inverse of
+// the diagonal block that the spine's step on B reads, zero-padded, in the
+// order of the threads: block t, elements q = 2h and 2h+1 of thread tid at
+// ((t * 4 + h) * NT + tid) * 2.  Every load of a step is then a coalesced
 // 16-byte load at a fixed offset from a uniform base.
-__host__ __device__ constexpr int64_t chunk_len(int st) { return (int64_t)(st + 1) * T * T; }
+__host__ __device__ constexpr int64_t chunk_len(int st) { return (int64_t)(st + 1) * SB * SB; }
 
-__device__ __forceinline__ int64_t slot(int t, int h, int tid) { return ((int64_t)(t * 2 + h) * NT + tid) * 2; }
+__device__ __forceinline__ int64_t slot(int t, int h, int tid) { return ((int64_t)(t * 4 + h) * NT + tid) * 2; }
 
 template <bool FWD>
 __device__ __forceinline__ int spine_block(const SolveArgs& S, int m) { return FWD ? m : S.NB - 1 - m; }
@@ -144,16 +176,15 @@ __device__ __forceinline__ void load_l(const SolveArgs& S, int B, int i, int p, 
   const int tid = threadIdx.x;
   const glb_d* c = S.ops + (int64_t)B * chunk_len(ST);
 #pragma unroll
-  for (int t = 0; t < ST; ++t) {
-    const d2 lo = *(const glb_d2*)(c + slot(t, 0, tid));
-    const d2 hi = *(const glb_d2*)(c + slot(t, 1, tid));
-    s.lf[t][0] = lo.x;
-    s.lf[t][1] = lo.y;
-    s.lf[t][2] = hi.x;
-    s.lf[t][3] = hi.y;
-  }
+  for (int t = 0; t < ST; ++t)
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const d2 v = *(const glb_d2*)(c + slot(t, h, tid));
+      s.lf[t][2 * h] = v.x;
+      s.lf[t][2 * h + 1] = v.y;
+    }
   // forward reads b (rows < n); back reads the forward result (all NBT rows)
-  const int64_t row = (int64_t)B * T + i;
+  const int64_t row = (int64_t)B * SB + i;
   const bool on = p < S.nrhs && (FWD ? row < S.a.n : true);
   s.bv = *opaque(on ? S.in + p * S.ldin + row : S.zero);
 }
@@ -162,28 +193,36 @@ template <int ST, bool FWD>
 __device__ __forceinline__ void load_d(const SolveArgs& S, int B, int i, int p, Stage<ST>& s) {
   const int tid = threadIdx.x;
   const glb_d* c = S.ops + (int64_t)B * chunk_len(ST);
-  const d2 lo = *(const glb_d2*)(c + slot(ST, 0, tid));
-  const d2 hi = *(const glb_d2*)(c + slot(ST, 1, tid));
-  s.df[0] = lo.x;
-  s.df[1] = lo.y;
-  s.df[2] = hi.x;
-  s.df[3] = hi.y;
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    const d2 v = *(const glb_d2*)(c + slot(ST, h, tid));
+    s.df[2 * h] = v.x;
+    s.df[2 * h + 1] = v.y;
+  }
   const bool hz = spine_has_z<ST, FWD>(S, B);
-  s.zv = aload<double>(opaque((hz && p < S.nrhs) ? S.z + ((int64_t)B * S.nrhs + p) * T + i : S.zero));
+  s.zv = aload<double>(opaque((hz && p < S.nrhs) ? S.z + ((int64_t)B * S.nrhs + p) * SB + i : S.zero));
 }
 
 // Ring slot of block N (N may lie up to ST before the first block).
 template <int ST>
 __device__ __forceinline__ int ring_slot(int N) { return (N + ST + 1) % (ST + 1); }
 
+// Stores a result of row `row` (rhs p) where this lane has one (on), else
+// into the sink: the publication buffer (and, back, the solution).
+template <bool FWD>
+__device__ __forceinline__ void publish(const SolveArgs& S, bool on, int64_t row, int p, double v) {
+  astore<double>((glb_d*)opaque(on ? S.pub + p * S.NBT + row : S.sink), v);
+  if (!FWD) *(glb_d*)opaque(on && p < S.nrhs && row < S.a.n ? S.out + p * S.ldout + row : S.sink) = v;
+}
+
 // One spine step on block B = spine_block(m), with the stage loaded for it;
 // refills the stage for step m + 2.  False if a wait gave up.
 //
 // The stage's registers are reloaded while the step's results are still in
 // flight.  Every value of the stage is therefore used once on every path
-// through the step (not only in the lanes that need it): a register whose
-// load might still be pending on some path would make the wave wait for that
-// load, and all later ones, before the reload.
+// through the step (not only in the lanes that need it), and every load and
+// store is issued on every path: otherwise the compiler cannot tell which
+// loads are still pending and waits for all of them before the reload.
 template <int ST, bool FWD>
 __device__ __forceinline__ bool spine_step(const SolveArgs& S, int m, Stage<ST>& s, lds_d* ring, lds_d* tl,
                                            lds_i* s_fail) {
@@ -194,23 +233,20 @@ __device__ __forceinline__ bool spine_step(const SolveArgs& S, int m, Stage<ST>&
   double bv = s.bv, zv = s.zv;
   asm volatile("" : "+v"(bv), "+v"(zv));
   // t = b - z - sum_d L(B,N) y_N  (back: L(N,B)^T x_N), one partial sum per
-  // neighbour so that the dependent chains are 4 long.  Neighbours past
-  // either end have zero tiles and read ring slots that were never written
-  // (zero).  The loops over the right-hand sides are unrolled to their bound,
-  // the first one taken always (nrhs >= 1).
+  // neighbour.  Neighbours past either end have zero blocks and read ring
+  // slots that were never written (zero).  The loops over the right-hand
+  // sides hold LDS reads only (counted apart from the global loads) and are
+  // not unrolled, which keeps the registers for the two stages; their first
+  // pass is always taken (nrhs >= 1).
   double mine = 0.0;
-#pragma unroll
-  for (int r = 0; r < RHS_MAX; ++r) {
-    if (r > 0 && r >= S.nrhs) break;
+  int r = 0;
+#pragma nounroll
+  do {
     double part[ST];
 #pragma unroll
     for (int d = 1; d <= ST; ++d) {
       const int N = FWD ? B - d : B + d;
-      const lds_d* yp = ring + ring_slot<ST>(N) * (T * RHS_MAX) + r * T + 4 * p;
-      double a0 = s.lf[d - 1][0] * yp[0];
-      a0 = fma(s.lf[d - 1][1], yp[1], a0);
-      a0 = fma(s.lf[d - 1][2], yp[2], a0);
-      part[d - 1] = fma(s.lf[d - 1][3], yp[3], a0);
+      part[d - 1] = dot8(s.lf[d - 1], ring + ring_slot<ST>(N) * (SB * RHS_MAX) + r * SB + QP * p);
     }
 #pragma unroll
     for (int w = 1; w < ST; w *= 2)
@@ -218,34 +254,50 @@ __device__ __forceinline__ bool spine_step(const SolveArgs& S, int m, Stage<ST>&
       for (int d = 0; d + w < ST; d += 2 * w) part[d] += part[d + w];
     const double acc = red8(part[0]);
     mine = p == r ? acc : mine;
-  }
+  } while (++r < S.nrhs);
   double zz = hz ? zv : 0.0;
-  if (hz && p < S.nrhs && unset(zz) && !await_value(S.z + ((int64_t)B * S.nrhs + p) * T + i, S.abort_flag, zz)) {
+  if (hz && p < S.nrhs && unset(zz) && !await_value(S.z + ((int64_t)B * S.nrhs + p) * SB + i, S.abort_flag, zz)) {
     *s_fail = 1;
     zz = 0.0;
   }
-  if (p < S.nrhs) tl[p * T + i] = (bv - zz) - mine;
+  const double tmine = (bv - zz) - mine;
+  if (p < S.nrhs) tl[p * SB + i] = tmine;
   // operands of step m + 2 (past the end: the last block again, unused)
   const int b2 = spine_block<FWD>(S, m + 2 < S.NB ? m + 2 : S.NB - 1);
   load_l<ST, FWD>(S, b2, i, p, s);
   __syncthreads();
-  // y_B = L(B,B)^{-1} t  (back: L(B,B)^{-T} t)
+  // Diagonal block, first half: the rows P completes (forward 0..31, back
+  // 32..63) take v = P t_h, the others u = t - v, where t_h is the half of t
+  // solved first (forward rows 0..31, back 32..63).
+  const int h0 = FWD ? 0 : T;            // first row of t_h
+  const bool direct = FWD ? i < T : i >= T;
   mine = 0.0;
-#pragma unroll
-  for (int r = 0; r < RHS_MAX; ++r) {
-    if (r > 0 && r >= S.nrhs) break;
-    const lds_d* tp = tl + r * T + 4 * p;
-    const double acc = red8(fma(s.df[3], tp[3], fma(s.df[2], tp[2], fma(s.df[1], tp[1], s.df[0] * tp[0]))));
+  r = 0;
+#pragma nounroll
+  do {
+    const double acc = red8(dot4(s.df, 0, tl + r * SB + h0 + 4 * p));
     mine = p == r ? acc : mine;
+  } while (++r < S.nrhs);
+  const int64_t row = (int64_t)B * SB + i;
+  lds_d* yslot = ring + ring_slot<ST>(B) * (SB * RHS_MAX);
+  if (p < S.nrhs) {
+    if (direct) yslot[p * SB + i] = mine;
+    else tl[p * SB + i] = tmine - mine;
   }
   // The stores are made by every lane (the publication buffers have RHS_MAX
-  // columns; the solution's masked-off lanes write the sink): a store that
-  // might be skipped would leave the compiler unsure how many operations
-  // follow each pending load, and it would wait for more of them.
-  const int64_t row = (int64_t)B * T + i;
-  if (p < S.nrhs) ring[ring_slot<ST>(B) * (T * RHS_MAX) + p * T + i] = mine;
-  astore<double>(S.pub + p * S.NBT + row, mine);
-  if (!FWD) *(glb_d*)opaque(p < S.nrhs && row < S.a.n ? S.out + p * S.ldout + row : S.sink) = mine;
+  // columns; masked-off lanes write the sink), for the reason given above.
+  publish<FWD>(S, direct, row, p, mine);
+  __syncthreads();
+  // Second half: the other rows take R u.
+  mine = 0.0;
+  r = 0;
+#pragma nounroll
+  do {
+    const double acc = red8(dot4(s.df, 4, tl + r * SB + (T - h0) + 4 * p));
+    mine = p == r ? acc : mine;
+  } while (++r < S.nrhs);
+  if (p < S.nrhs && !direct) yslot[p * SB + i] = mine;
+  publish<FWD>(S, !direct, row, p, mine);
   load_d<ST, FWD>(S, b2, i, p, s);
   __syncthreads();
   return *s_fail == 0;
@@ -254,7 +306,7 @@ __device__ __forceinline__ bool spine_step(const SolveArgs& S, int m, Stage<ST>&
 template <int ST, bool FWD>
 __device__ __forceinline__ void spine(const SolveArgs& S, lds_d* ring, lds_d* tl, lds_i* s_fail) {
   const int tid = threadIdx.x, i = tid >> 3, p = tid & 7;
-  for (int e = tid; e < (ST + 1) * T * RHS_MAX; e += NT) ring[e] = 0.0;
+  for (int e = tid; e < (ST + 1) * SB * RHS_MAX; e += NT) ring[e] = 0.0;
   Stage<ST> s0, s1;
   const int b1 = spine_block<FWD>(S, S.NB > 1 ? 1 : 0);
   load_l<ST, FWD>(S, spine_block<FWD>(S, 0), i, p, s0);
@@ -262,16 +314,22 @@ __device__ __forceinline__ void spine(const SolveArgs& S, lds_d* ring, lds_d* tl
   load_l<ST, FWD>(S, b1, i, p, s1);
   load_d<ST, FWD>(S, b1, i, p, s1);
   __syncthreads();
-  for (int m = 0; m < S.NB; m += 2) {
+  // Steps in pairs, both always taken, so that each stage is refilled on every
+  // path through the loop body (a stage that might keep its old value would
+  // be copied at the loop's end, and the copy waits for the loads).
+  int m = 0;
+  for (; m + 1 < S.NB; m += 2) {
     if (!spine_step<ST, FWD>(S, m, s0, ring, tl, s_fail)) return;
-    if (m + 1 < S.NB && !spine_step<ST, FWD>(S, m + 1, s1, ring, tl, s_fail)) return;
+    if (!spine_step<ST, FWD>(S, m + 1, s1, ring, tl, s_fail)) return;
   }
+  if (m < S.NB) spine_step<ST, FWD>(S, m, s0, ring, tl, s_fail);
 }
 
 // Helper for block B: z_B = sum over the far neighbours N of L(B,N) y_N
 // (forward, N = B-KS .. B-ST-1) or L(N,B)^T x_N (back, N = B+KS .. B+ST+1),
-// taken in the order they are published, G blocks per round of loads.
-// Thread (i, p): row (column) i of B, rows 4p .. 4p+3 of each N.
+// taken in the order they are published, G blocks per round of loads, one
+// right-hand side per pass.  Thread (i, p): row (column) i of B, rows
+// 8p .. 8p+7 of each N.
 template <int ST, bool FWD>
 __device__ __forceinline__ bool helper(const SolveArgs& S, int B, lds_i* s_flag) {
   const int tid = threadIdx.x, i = tid >> 3, p = tid & 7;
@@ -279,33 +337,23 @@ __device__ __forceinline__ bool helper(const SolveArgs& S, int B, lds_i* s_flag)
                        : (B + S.KS < S.NB - 1 ? B + S.KS : S.NB - 1) - (B + ST + 1) + 1;
   const int N0 = FWD ? (B - S.KS > 0 ? B - S.KS : 0) : (B + S.KS < S.NB - 1 ? B + S.KS : S.NB - 1);
   const int dir = FWD ? 1 : -1;
-  for (int r0 = 0; r0 < S.nrhs; r0 += HR) {
-    const int nr = S.nrhs - r0 < HR ? S.nrhs - r0 : HR;
-    double acc[HR];
-#pragma unroll
-    for (int rr = 0; rr < HR; ++rr) acc[rr] = 0.0;
+  for (int r = 0; r < S.nrhs; ++r) {
+    double acc = 0.0;
     for (int g0 = 0; g0 < nfar; g0 += G) {
-      double lf[G][4], yv[G][HR][4];
+      double lf[G][QP], yv[G][QP];
       bool miss = false;
 #pragma unroll
       for (int g = 0; g < G; ++g) {
         const bool on = g0 + g < nfar;
         const int N = N0 + dir * (g0 + g);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int64_t gi = FWD ? (int64_t)B * T + i : (int64_t)N * T + 4 * p + q;
-          const int64_t gj = FWD ? (int64_t)N * T + 4 * p + q : (int64_t)B * T + i;
+        for (int q = 0; q < QP; ++q) {
+          const int64_t gi = FWD ? (int64_t)B * SB + i : (int64_t)N * SB + QP * p + q;
+          const int64_t gj = FWD ? (int64_t)N * SB + QP * p + q : (int64_t)B * SB + i;
           lf[g][q] = *band_or_zero(S, on ? gi : S.a.n, gj);
+          yv[g][q] = aload<double>(opaque(on ? S.pub + r * S.NBT + (int64_t)N * SB + QP * p + q : S.zero));
+          miss |= unset(yv[g][q]);
         }
-#pragma unroll
-        for (int rr = 0; rr < HR; ++rr)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const bool v_on = on && rr < nr;
-            yv[g][rr][q] =
-                aload<double>(opaque(v_on ? S.pub + (r0 + rr) * S.NBT + (int64_t)N * T + 4 * p + q : S.zero));
-            miss |= unset(yv[g][rr][q]);
-          }
       }
       if (__syncthreads_or(miss)) {
         // Not all published yet: thread 0 waits for the newest block of the
@@ -315,7 +363,7 @@ __device__ __forceinline__ bool helper(const SolveArgs& S, int B, lds_i* s_flag)
         const int Nl = N0 + dir * (g0 + gl);
         if (tid == 0) {
           double v;
-          *s_flag = await_value(S.pub + (r0 + nr - 1) * S.NBT + (int64_t)Nl * T + T - 1, S.abort_flag, v) ? 0 : 1;
+          *s_flag = await_value(S.pub + r * S.NBT + (int64_t)Nl * SB + SB - 1, S.abort_flag, v) ? 0 : 1;
         }
         __syncthreads();
         if (*s_flag) return false;
@@ -324,26 +372,19 @@ __device__ __forceinline__ bool helper(const SolveArgs& S, int B, lds_i* s_flag)
         for (int g = 0; g < G; ++g) {
           const int N = N0 + dir * (g0 + g);
 #pragma unroll
-          for (int rr = 0; rr < HR; ++rr)
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-              if (ok && unset(yv[g][rr][q]))
-                ok = await_value(S.pub + (r0 + rr) * S.NBT + (int64_t)N * T + 4 * p + q, S.abort_flag, yv[g][rr][q]);
+          for (int q = 0; q < QP; ++q)
+            if (ok && unset(yv[g][q]))
+              ok = await_value(S.pub + r * S.NBT + (int64_t)N * SB + QP * p + q, S.abort_flag, yv[g][q]);
         }
         if (__syncthreads_or(!ok)) return false;
       }
 #pragma unroll
       for (int g = 0; g < G; ++g)
 #pragma unroll
-        for (int rr = 0; rr < HR; ++rr)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) acc[rr] = fma(lf[g][q], yv[g][rr][q], acc[rr]);
+        for (int q = 0; q < QP; ++q) acc = fma(lf[g][q], yv[g][q], acc);
     }
-#pragma unroll
-    for (int rr = 0; rr < HR; ++rr) {
-      const double s = red8(acc[rr]);
-      if (rr < nr && p == ((r0 + rr) & 7)) astore<double>(S.z + ((int64_t)B * S.nrhs + r0 + rr) * T + i, s);
-    }
+    const double s = red8(acc);
+    if (p == (r & 7)) astore<double>(S.z + ((int64_t)B * S.nrhs + r) * SB + i, s);
   }
   return true;
 }
@@ -352,8 +393,8 @@ __device__ __forceinline__ bool helper(const SolveArgs& S, int B, lds_i* s_flag)
 
 template <int ST, bool FWD>
 __global__ void __launch_bounds__(NT) solve_kernel(SolveArgs S) {
-  __shared__ double ring[(ST + 1) * T * RHS_MAX];
-  __shared__ double tl[T * RHS_MAX];
+  __shared__ double ring[(ST + 1) * SB * RHS_MAX];
+  __shared__ double tl[SB * RHS_MAX];
   __shared__ int s_ticket, s_flag;
   const int nhelp = S.KS > ST ? S.NB - ST - 1 : 0;
   if (threadIdx.x == 0) s_flag = 0;
@@ -389,9 +430,10 @@ __global__ void solve_fill_kernel(glb_d* p, int64_t len, int64_t stride, unsigne
   }
 }
 
-// Per diagonal tile, L(C,C)^{-T} (row-major): lanes 0..T-1 hold the rows of
-// L(C,C), lanes T..2T-1 the identity rows, solved against L(C,C) column by column.
-__global__ void __launch_bounds__(64) tri_inv_kernel(Band a, int NB, glb_d* dinvt) {
+// Per tile C, L(C,C)^{-T} (row-major): lanes 0..T-1 hold the rows of L(C,C),
+// lanes T..2T-1 the identity rows, solved against L(C,C) column by column.
+// Tiles past the last row come out as the identity.
+__global__ void __launch_bounds__(64) tri_inv_kernel(Band a, glb_d* dinvt) {
   const int C = blockIdx.x, lane = threadIdx.x;
   double row[T];
   const int64_t i = (int64_t)C * T + lane;
@@ -419,30 +461,80 @@ __global__ void __launch_bounds__(64) tri_inv_kernel(Band a, int NB, glb_d* dinv
   }
 }
 
+// The operators of the diagonal block B = [A 0; C D] (tiles 2B and 2B+1),
+// into LDS with pitch LP: A^{-1} (sa), D^{-1} (sd) from tri_inv_kernel
+// (A^{-1}(r, c) = dinvt[c T + r]), and in sc C A^{-1} (forward) or D^{-1} C
+// (back).
+template <bool FWD>
+__device__ __forceinline__ void block_operators(const Band& a, int B, const glb_d* dinvt, lds_d* sa, lds_d* sd,
+                                                lds_d* sc) {
+  const int tid = threadIdx.x;
+  const glb_d* da = dinvt + (int64_t)(2 * B) * T * T;
+  const glb_d* dd = da + T * T;
+  const int64_t r0 = (int64_t)B * SB;
+  for (int e = tid; e < T * T; e += NT) {
+    const int r = e % T, c = e / T;
+    sa[r * LP + c] = da[c * T + r];
+    sd[r * LP + c] = dd[c * T + r];
+    sc[r * LP + c] = a.ld(r0 + T + r, r0 + c);
+  }
+  __syncthreads();
+  // two elements per thread, in row r (both inverses lower triangular)
+  const int r = tid >> 4, c0 = (tid & 15) * 2;
+  double m[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int c = c0 + u;
+    double v = 0.0;
+    if (FWD)
+      for (int k = c; k < T; ++k) v = fma(sc[r * LP + k], sa[k * LP + c], v);
+    else
+      for (int k = 0; k <= r; ++k) v = fma(sd[r * LP + k], sc[k * LP + c], v);
+    m[u] = v;
+  }
+  __syncthreads();
+  sc[r * LP + c0] = m[0];
+  sc[r * LP + c0 + 1] = m[1];
+  __syncthreads();
+}
+
 // Writes the operand buffer of one direction (layout at chunk_len): per
-// block B, the ST tiles of L next to it (zero outside the band and past
-// either end) and the inverse of its diagonal tile, from dinvt.
+// block B, the ST blocks of L next to it (zero outside the band and past
+// either end), then for each thread (i, p), columns 4p .. 4p+3 of row i of
+// the diagonal block's operators P and R:
+//   forward  P = [A^{-1}; C A^{-1}],   R = [0; D^{-1}]
+//   back     P = [(D^{-1} C)^T; D^{-T}], R = [A^{-T}; 0]
 template <int ST, bool FWD>
 __global__ void __launch_bounds__(NT) prep_kernel(Band a, int NB, const glb_d* dinvt, glb_d* ops) {
+  __shared__ double sa[T * LP], sd[T * LP], sc[T * LP];
   const int B = blockIdx.x, tid = threadIdx.x, i = tid >> 3, p = tid & 7;
+  block_operators<FWD>(a, B, dinvt, (lds_d*)sa, (lds_d*)sd, (lds_d*)sc);
   glb_d* c = ops + (int64_t)B * chunk_len(ST);
 #pragma unroll
   for (int t = 0; t <= ST; ++t) {
-    double v[4];
+    double v[QP];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < QP; ++q) {
       if (t < ST) {
         const int N = FWD ? B - (t + 1) : B + (t + 1);
-        const int64_t gi = FWD ? (int64_t)B * T + i : (int64_t)N * T + 4 * p + q;
-        const int64_t gj = FWD ? (int64_t)N * T + 4 * p + q : (int64_t)B * T + i;
+        const int64_t gi = FWD ? (int64_t)B * SB + i : (int64_t)N * SB + QP * p + q;
+        const int64_t gj = FWD ? (int64_t)N * SB + QP * p + q : (int64_t)B * SB + i;
         v[q] = (N >= 0 && N < NB && a.in_band(gi, gj)) ? *a.at(gi, gj) : 0.0;
       } else {
-        const glb_d* di = dinvt + (int64_t)B * T * T;
-        v[q] = FWD ? di[(4 * p + q) * T + i] : di[i * T + 4 * p + q];
+        const int cc = 4 * p + (q & 3);
+        const bool lo = i < T;
+        const int ih = lo ? i : i - T;
+        if (q < 4) {
+          if (FWD) v[q] = lo ? sa[ih * LP + cc] : sc[ih * LP + cc];
+          else v[q] = lo ? sc[cc * LP + ih] : sd[cc * LP + ih];
+        } else {
+          if (FWD) v[q] = lo ? 0.0 : sd[ih * LP + cc];
+          else v[q] = lo ? sa[cc * LP + ih] : 0.0;
+        }
       }
     }
-    *(glb_d2*)(c + slot(t, 0, tid)) = d2{v[0], v[1]};
-    *(glb_d2*)(c + slot(t, 1, tid)) = d2{v[2], v[3]};
+#pragma unroll
+    for (int h = 0; h < 4; ++h) *(glb_d2*)(c + slot(t, h, tid)) = d2{v[2 * h], v[2 * h + 1]};
   }
 }
 
@@ -457,11 +549,11 @@ void launch_pair(const Band& a, const glb_d* dinvt, glb_d* ops, const SolveArgs&
 
 // Blocks of the band the spine applies itself: all of them up to ST_MAX,
 // rounded up to an instantiated width; beyond, ST_MAX and helpers.
-inline int spine_width(int KS) { return KS <= 1 ? 1 : KS <= 2 ? 2 : KS <= 4 ? 4 : ST_MAX; }
+inline int spine_width(int KS) { return KS <= 1 ? 1 : ST_MAX; }
 
-inline int tile_blocks_of(int64_t n, int64_t k) {
-  const int NB = (int)((n + T - 1) / T);
-  int KS = (int)((k + T - 1) / T);
+inline int blocks_of_band(int64_t n, int64_t k) {
+  const int NB = (int)((n + SB - 1) / SB);
+  int KS = (int)((k + SB - 1) / SB);
   if (KS > NB - 1) KS = NB - 1 > 0 ? NB - 1 : 0;
   return KS;
 }
@@ -473,21 +565,21 @@ inline int tile_blocks_of(int64_t n, int64_t k) {
 // element and (at 128) the sink; then the publication area, 4 * RHS_MAX * NBT
 // doubles (forward result, back result, forward and back helper sums, RHS_MAX
 // * NBT each, of which a pass of nrhs right-hand sides uses the first
-// nrhs * NBT); then the inverted diagonal tiles,
-// NB * T * T doubles; then the operand buffer, NB * chunk_len(ST) doubles.
+// nrhs * NBT); then the inverted tiles, 2 * NB * T * T doubles; then the
+// operand buffer, NB * chunk_len(ST) doubles.
 size_t bandchol_solve_workspace(int64_t n, int64_t k) {
   using namespace bandchol_solve;
-  const int64_t NB = (n + T - 1) / T, NBT = NB * T;
-  const int ST = spine_width(tile_blocks_of(n, k));
-  return 256 + sizeof(double) * ((size_t)(4 * RHS_MAX + T) * NBT + (size_t)NB * chunk_len(ST));
+  const int64_t NB = (n + SB - 1) / SB, NBT = NB * SB;
+  const int ST = spine_width(blocks_of_band(n, k));
+  return 256 + sizeof(double) * ((size_t)4 * RHS_MAX * NBT + (size_t)2 * NB * T * T + (size_t)NB * chunk_len(ST));
 }
 
 hipError_t bandchol_solve_launch(int64_t n, int64_t k, int64_t nrhs, const double* ab, int64_t ldab, double* b,
                                  int64_t ldb, void* ws, int num_cus, hipStream_t st) {
   using namespace bandchol_solve;
-  const int NB = (int)((n + T - 1) / T);
-  const int64_t NBT = (int64_t)NB * T;
-  const int KS = tile_blocks_of(n, k);
+  const int NB = (int)((n + SB - 1) / SB);
+  const int64_t NBT = (int64_t)NB * SB;
+  const int KS = blocks_of_band(n, k);
   const int ST = spine_width(KS);
   char* base = (char*)ws;
   unsigned* queues = (unsigned*)base;
@@ -496,9 +588,9 @@ hipError_t bandchol_solve_launch(int64_t n, int64_t k, int64_t nrhs, const doubl
   glb_d* sink = (glb_d*)(base + 128);
   glb_d* pubarea = (glb_d*)(base + 256);
   glb_d* dinvt = pubarea + (size_t)4 * RHS_MAX * NBT;
-  glb_d* ops = dinvt + (size_t)NB * T * T;
+  glb_d* ops = dinvt + (size_t)2 * NB * T * T;
   const Band a{(glb_d*)const_cast<double*>(ab), n, k, ldab};
-  tri_inv_kernel<<<NB, 64, 0, st>>>(a, NB, dinvt);
+  tri_inv_kernel<<<2 * NB, 64, 0, st>>>(a, dinvt);
   const int nhelp = KS > ST ? NB - ST - 1 : 0;
   // one workgroup per CU at most: the spine keeps a CU to itself
   const int grid = 1 + nhelp < num_cus ? 1 + nhelp : num_cus;
@@ -516,12 +608,8 @@ hipError_t bandchol_solve_launch(int64_t n, int64_t k, int64_t nrhs, const doubl
     const int64_t fg = (4 * len + 255) / 256;
     solve_fill_kernel<<<(unsigned)(fg < 2048 ? fg : 2048), 256, 0, st>>>(pubarea, len, (int64_t)stride, queues,
                                                                          abort_flag, zero);
-    switch (ST) {
-      case 1: launch_pair<1>(a, dinvt, ops, F, Bk, grid, st); break;
-      case 2: launch_pair<2>(a, dinvt, ops, F, Bk, grid, st); break;
-      case 4: launch_pair<4>(a, dinvt, ops, F, Bk, grid, st); break;
-      default: launch_pair<ST_MAX>(a, dinvt, ops, F, Bk, grid, st); break;
-    }
+    if (ST == 1) launch_pair<1>(a, dinvt, ops, F, Bk, grid, st);
+    else launch_pair<ST_MAX>(a, dinvt, ops, F, Bk, grid, st);
   }
   return hipGetLastError();
 }
