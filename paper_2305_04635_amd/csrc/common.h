@@ -241,44 +241,90 @@ __device__ __forceinline__ v4_t<F> blk_trsm_lds(const lds_t<F>* x, const lds_t<F
 // while lanes T..2T-1 carry the identity rows, in one wave.
 //
 // The pivot chain runs in L D L^T form.  For column j the unscaled column
-// w_ij = A'(i, j) is final once column j-1 has been applied; it is broadcast
-// with readlane (no LDS traffic, so the sweep does not queue behind the MFMA
-// operand reads of the other waves) and every row is updated by
-// A'(i, l) -= (w_ij / d_j) w_lj, l > j.  Only one reciprocal per column is on
-// the dependency chain: the next pivot d_{j+1} = A'(j+1,j+1) - w_{j+1,j}^2 / d_j
-// is formed directly from two values known before the reciprocal.  The square
-// roots are taken once at the end, off the chain: both the factor rows (unit
-// factor l, L = l D^{1/2}) and the identity rows (which now hold l^{-T} D^{-1},
-// and L^{-T} = l^{-T} D^{-1/2}) are scaled column by column by sqrt(d_c).
+// w_ij = A'(i, j) is final once column j-1 has been applied; every row is
+// updated by A'(i, l) -= (w_ij / d_j) w_lj, l > j.  Only one reciprocal per
+// column is on the dependency chain: the next pivot
+// d_{j+1} = A'(j+1,j+1) - w_{j+1,j}^2 / d_j is formed directly from two values
+// known before the reciprocal.  The square roots are taken once at the end, off
+// the chain: both the factor rows (unit factor l, L = l D^{1/2}) and the
+// identity rows (which now hold l^{-T} D^{-1}, and L^{-T} = l^{-T} D^{-1/2}) are
+// scaled column by column by sqrt(d_c).
+//
+// Two levels: the columns of each half of the tile are swept with updates
+// inside that half only, the broadcasts of w_lj done by readlane; the first
+// half's update of the second half, A'(i, H+c) -= sum_j q_ij d_j q_{H+c,j}
+// (q_ij = w_ij / d_j, the multipliers left in the first half's columns) is one
+// rank-H product on the matrix cores, through LDS.  This halves the
+// broadcasts, which bound a one-level sweep (two readlanes and the wait
+// states after them per element).  `sq` holds at least H x (2T+1) elements
+// and `sd` H, both free LDS of this wave (no other wave touches them meanwhile).
+//
 // Afterwards lane i < T holds row i of L (upper part unspecified) and lane
 // T+b holds row b of L^{-T}.  Returns the first local column whose pivot is
 // not > 0 (zero, negative or NaN), or -1.
 template <typename F>
-__device__ __forceinline__ int sweep_ldlt(F (&row)[T]) {
+__device__ __forceinline__ void sweep_half(F (&row)[T], int j0, F& dcur, F& d_mine, int& fail) {
   const int lane = lane_id();
-  F d_mine = F(1);                        // lane c keeps pivot c
-  F dcur = readlane(row[0], 0);
-  int fail = -1;
+  constexpr int H = T / 2;
   // Straight-line code (no exit per column) so that the scheduler can overlap
   // column j+1's pivot chain with column j's row updates.
 #pragma unroll
-  for (int j = 0; j < T; ++j) {
+  for (int jj = 0; jj < H; ++jj) {
+    const int j = j0 + jj;
     const F d = dcur;
     fail = (fail < 0 && !(d > F(0))) ? j : fail;
     const F w = row[j];
     F p = F(0), wn = F(0);
-    if (j + 1 < T) {
+    if (jj + 1 < H) {
       p = readlane(row[j + 1], j + 1);
       wn = readlane(w, j + 1);
     }
     const F dinv = recip(d);
     d_mine = (lane == j) ? d : d_mine;
-    if (j + 1 < T) dcur = fma(-(wn * wn), dinv, p);
+    if (jj + 1 < H) dcur = fma(-(wn * wn), dinv, p);
     const F q = w * dinv;
     row[j] = (lane == j) ? F(1) : q;
 #pragma unroll
-    for (int l = j + 1; l < T; ++l) row[l] = fma(-q, readlane(w, l), row[l]);
+    for (int l = j + 1; l < j0 + H; ++l) row[l] = fma(-q, readlane(w, l), row[l]);
   }
+}
+
+template <typename F>
+__device__ __forceinline__ int sweep_ldlt(F (&row)[T], lds_t<F>* sq, lds_t<F>* sd) {
+  const int lane = lane_id();
+  constexpr int H = T / 2;
+  constexpr int QP = 2 * T + 1;           // LDS pitch of a column over the 64 lanes
+  F d_mine = F(1);                        // lane c keeps pivot c
+  F dcur = readlane(row[0], 0);
+  int fail = -1;
+  sweep_half(row, 0, dcur, d_mine, fail);
+  // Second half -= Q D Q_2^T: Q (64 x H) = the first half's columns of all
+  // lanes, Q_2 its rows H..T-1.  Output tile b (lanes 16b .. 16b+15) of the
+  // 64 x H product accumulates X Y^T with X = rows of Q and Y = Q_2 D.  Within
+  // one wave LDS operations complete in order, so no barrier is needed.
+#pragma unroll
+  for (int j = 0; j < H; ++j) sq[j * QP + lane] = row[j];
+  if (lane < H) sd[lane] = d_mine;
+  v4_t<F> acc[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) acc[b] = v4_t<F>{0, 0, 0, 0};
+#pragma unroll
+  for (int q4 = 0; q4 < H / 4; ++q4) {
+    const int kk = 4 * q4 + (lane >> 4);
+    const F y = sq[kk * QP + H + (lane & 15)] * sd[kk];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[b] = mfma_xyt(sq[kk * QP + 16 * b + (lane & 15)], y, acc[b]);
+  }
+  // accumulator form (row 16b + l%16, column acc_col0 + ACC_STEP r) -> LDS column-major -> lane rows
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      sq[(Prec<F>::acc_col0(lane) + Prec<F>::ACC_STEP * r) * QP + 16 * b + (lane & 15)] = acc[b][r];
+#pragma unroll
+  for (int c = 0; c < H; ++c) row[H + c] -= sq[c * QP + lane];
+  dcur = readlane(row[H], H);
+  sweep_half(row, H, dcur, d_mine, fail);
   const F s_mine = prec_sqrt(d_mine);
 #pragma unroll
   for (int c = 0; c < T; ++c) row[c] *= readlane(s_mine, c);

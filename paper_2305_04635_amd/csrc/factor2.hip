@@ -245,32 +245,33 @@ struct SpineLds {
   lds_t<F>* lcc_prev;
 };
 
+// Wave 0: the sweep of the staged diagonal tile; L(C,C) and L(C,C)^{-T} go to
+// LDS only (both conflict-free: pitch LP); another wave copies them to global
+// memory off the critical path.  Takes only scalars and LDS pointers (no
+// structures): a structure passed to a noinline function is read back from the
+// stack, a memory round trip at the head of the chain.
 template <typename F>
-__device__ __attribute__((noinline)) void spine_sweep(const Args<F>& A_, int64_t C, const SpineLds<F>& S_,
+__device__ __attribute__((noinline)) void spine_sweep(lds_t<F>* diag, lds_t<F>* lcc, lds_t<F>* linvt, int64_t col0,
+                                                      int64_t n, unsigned long long* first_fail, glb_i* abort_flag,
                                                       lds_i* s_fail) {
-  const Args<F> A = A_;
-  const SpineLds<F> S = S_;
   const int lane = lane_id();
-  const BandT<F>& a = A.a;
   F row[T];
 #pragma unroll
-  for (int c = 0; c < T; ++c) row[c] = lane < T ? S.diag[c * LP + lane] : ((lane - T) == c ? F(1) : F(0));
-  const int fail = sweep_ldlt(row);
+  for (int c = 0; c < T; ++c) row[c] = lane < T ? diag[c * LP + lane] : ((lane - T) == c ? F(1) : F(0));
+  const int fail = sweep_ldlt(row, diag, lcc);  // both free while this wave sweeps
   if (fail >= 0) {
     if (lane == 0) {
       *s_fail = fail;
-      const long long col = (long long)C * T + fail;
-      if (col < a.n) atomicMin(A.w.first_fail, (unsigned long long)(col + 1));
-      __hip_atomic_store(A.w.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const long long col = (long long)col0 + fail;
+      if (col < n) atomicMin(first_fail, (unsigned long long)(col + 1));
+      __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     return;
   }
-  // L(C,C) and L(C,C)^{-T} go to LDS only (both conflict-free: pitch LP);
-  // another wave copies them to global memory off the critical path.
 #pragma unroll
   for (int c = 0; c < T; ++c) {
-    if (lane < T) S.lcc[c * LP + lane] = row[c];
-    else S.linvt[(lane - T) * LP + c] = row[c];
+    if (lane < T) lcc[c * LP + lane] = row[c];
+    else linvt[(lane - T) * LP + c] = row[c];
   }
 }
 
@@ -427,7 +428,7 @@ __device__ void spine(const Args<F>& A, lds_t<F>* base, lds_i* s_fail, lds_i* s_
       }
     }
     // phase A
-    if (wave == 0) spine_sweep(A, C, S, s_fail);
+    if (wave == 0) spine_sweep<F>(S.diag, S.lcc, S.linvt, C * T, A.a.n, A.w.first_fail, A.w.abort_flag, s_fail);
     else if (next && A.K >= 1) spine_prepare(A, C, S, s_fail);
     else if (next && wave >= 1) {
       const int bi = (wave >= 2), bj = (wave == 3);

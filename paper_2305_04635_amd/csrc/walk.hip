@@ -96,7 +96,7 @@ __device__ __attribute__((noinline)) void walk_sweep(const Band& a_, int64_t C, 
   double row[T];
 #pragma unroll
   for (int c = 0; c < T; ++c) row[c] = lane < T ? L.diag[c * LP + lane] : ((lane - T) == c ? 1.0 : 0.0);
-  const int fail = sweep_ldlt(row);
+  const int fail = sweep_ldlt(row, L.diag, lt);  // both free while this wave sweeps
   if (fail >= 0) {
     if (lane == 0) *s_fail = fail;
     return;
