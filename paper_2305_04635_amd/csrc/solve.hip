@@ -46,7 +46,6 @@ constexpr int SB = 64;               // rows per block
 constexpr int NT = 512;              // threads: (i, p) = (tid / 8, tid % 8), row i, columns 8p .. 8p+7
 constexpr int QP = 8;                // columns per thread
 constexpr int RHS_MAX = 8;           // right-hand sides per launch (thread p completes r = p)
-constexpr int G = 2;                 // blocks a helper loads at once
 constexpr int ST_MAX = 2;            // most blocks the spine applies itself
 constexpr long long SPIN_LIMIT = 1LL << 24;
 constexpr long long UNSET = 0x7FF4DEADBEEF0001LL;   // a signalling NaN
@@ -64,7 +63,7 @@ struct SolveArgs {
   int64_t ldout;
   unsigned* queue;        // ticket counter
   glb_i* abort_flag;      // 2 = a wait exceeded its bound
-  const glb_d* zero;      // a zero: masked-off lanes load it, so that every load is unconditional
+  const glb_d* zero;      // QP zeros: masked-off lanes load them, so that every load is unconditional
   glb_d* sink;            // masked-off lanes store here, so that every store is unconditional
 };
 
@@ -303,6 +302,8 @@ __device__ __forceinline__ bool spine_step(const SolveArgs& S, int m, Stage<ST>&
   return *s_fail == 0;
 }
 
+// Inlined into the kernel: a call here costs more than the few registers the
+// kernel then spills (measured both ways).
 template <int ST, bool FWD>
 __device__ __forceinline__ void spine(const SolveArgs& S, lds_d* ring, lds_d* tl, lds_i* s_fail) {
   const int tid = threadIdx.x, i = tid >> 3, p = tid & 7;
@@ -327,64 +328,81 @@ __device__ __forceinline__ void spine(const SolveArgs& S, lds_d* ring, lds_d* tl
 
 // Helper for block B: z_B = sum over the far neighbours N of L(B,N) y_N
 // (forward, N = B-KS .. B-ST-1) or L(N,B)^T x_N (back, N = B+KS .. B+ST+1),
-// taken in the order they are published, G blocks per round of loads, one
-// right-hand side per pass.  Thread (i, p): row (column) i of B, rows
-// 8p .. 8p+7 of each N.
-template <int ST, bool FWD>
+// taken in the order they are published, G blocks and RH right-hand sides per
+// round of loads.  All right-hand sides of a block go through the same round
+// (RH = RHS_MAX, L loaded once per block), or with one right-hand side G
+// blocks do (RH = 1): either way the sums are complete one round trip after the
+// newest block appears.  Thread (i, p): row (column) i of B, rows 8p .. 8p+7
+// of each N.
+template <int ST, bool FWD, int G, int RH>
 __device__ __forceinline__ bool helper(const SolveArgs& S, int B, lds_i* s_flag) {
   const int tid = threadIdx.x, i = tid >> 3, p = tid & 7;
   const int nfar = FWD ? (B - ST - 1) - (B - S.KS > 0 ? B - S.KS : 0) + 1
                        : (B + S.KS < S.NB - 1 ? B + S.KS : S.NB - 1) - (B + ST + 1) + 1;
   const int N0 = FWD ? (B - S.KS > 0 ? B - S.KS : 0) : (B + S.KS < S.NB - 1 ? B + S.KS : S.NB - 1);
   const int dir = FWD ? 1 : -1;
-  for (int r = 0; r < S.nrhs; ++r) {
-    double acc = 0.0;
-    for (int g0 = 0; g0 < nfar; g0 += G) {
-      double lf[G][QP], yv[G][QP];
-      bool miss = false;
+  double acc[RH];
 #pragma unroll
-      for (int g = 0; g < G; ++g) {
-        const bool on = g0 + g < nfar;
-        const int N = N0 + dir * (g0 + g);
+  for (int r = 0; r < RH; ++r) acc[r] = 0.0;
+  for (int g0 = 0; g0 < nfar; g0 += G) {
+    double lf[G][QP], yv[G][RH][QP];
+    bool miss = false;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const bool on = g0 + g < nfar;
+      const int N = N0 + dir * (g0 + g);
+#pragma unroll
+      for (int q = 0; q < QP; ++q) {
+        const int64_t gi = FWD ? (int64_t)B * SB + i : (int64_t)N * SB + QP * p + q;
+        const int64_t gj = FWD ? (int64_t)N * SB + QP * p + q : (int64_t)B * SB + i;
+        lf[g][q] = *band_or_zero(S, on ? gi : S.a.n, gj);
+      }
+      const glb_d* yb = S.pub + (int64_t)N * SB + QP * p;
+#pragma unroll
+      for (int r = 0; r < RH; ++r) {
+        const glb_d* yr = opaque(on && r < S.nrhs ? yb + r * S.NBT : S.zero);   // QP zeros there
 #pragma unroll
         for (int q = 0; q < QP; ++q) {
-          const int64_t gi = FWD ? (int64_t)B * SB + i : (int64_t)N * SB + QP * p + q;
-          const int64_t gj = FWD ? (int64_t)N * SB + QP * p + q : (int64_t)B * SB + i;
-          lf[g][q] = *band_or_zero(S, on ? gi : S.a.n, gj);
-          yv[g][q] = aload<double>(opaque(on ? S.pub + r * S.NBT + (int64_t)N * SB + QP * p + q : S.zero));
-          miss |= unset(yv[g][q]);
+          yv[g][r][q] = aload<double>(yr + q);
+          miss |= unset(yv[g][r][q]);
         }
       }
-      if (__syncthreads_or(miss)) {
-        // Not all published yet: thread 0 waits for the newest block of the
-        // round (one poller per workgroup), then every missing element is
-        // awaited on its own.
-        const int gl = (nfar - g0 < G ? nfar - g0 : G) - 1;
-        const int Nl = N0 + dir * (g0 + gl);
-        if (tid == 0) {
-          double v;
-          *s_flag = await_value(S.pub + r * S.NBT + (int64_t)Nl * SB + SB - 1, S.abort_flag, v) ? 0 : 1;
-        }
-        __syncthreads();
-        if (*s_flag) return false;
-        bool ok = true;
+    }
+    if (__syncthreads_or(miss)) {
+      // Not all published yet: thread 0 waits for the last element of the
+      // newest block's last right-hand side (one poller per workgroup), then
+      // every missing element is awaited on its own.
+      const int gl = (nfar - g0 < G ? nfar - g0 : G) - 1;
+      const int Nl = N0 + dir * (g0 + gl);
+      if (tid == 0) {
+        double v;
+        *s_flag = await_value(S.pub + (S.nrhs - 1) * S.NBT + (int64_t)Nl * SB + SB - 1, S.abort_flag, v) ? 0 : 1;
+      }
+      __syncthreads();
+      if (*s_flag) return false;
+      bool ok = true;
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-          const int N = N0 + dir * (g0 + g);
+      for (int g = 0; g < G; ++g) {
+        const glb_d* yb = S.pub + (int64_t)(N0 + dir * (g0 + g)) * SB + QP * p;
+#pragma unroll
+        for (int r = 0; r < RH; ++r)
 #pragma unroll
           for (int q = 0; q < QP; ++q)
-            if (ok && unset(yv[g][q]))
-              ok = await_value(S.pub + r * S.NBT + (int64_t)N * SB + QP * p + q, S.abort_flag, yv[g][q]);
-        }
-        if (__syncthreads_or(!ok)) return false;
+            if (ok && unset(yv[g][r][q])) ok = await_value(yb + r * S.NBT + q, S.abort_flag, yv[g][r][q]);
       }
-#pragma unroll
-      for (int g = 0; g < G; ++g)
-#pragma unroll
-        for (int q = 0; q < QP; ++q) acc = fma(lf[g][q], yv[g][q], acc);
+      if (__syncthreads_or(!ok)) return false;
     }
-    const double s = red8(acc);
-    if (p == (r & 7)) astore<double>(S.z + ((int64_t)B * S.nrhs + r) * SB + i, s);
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int r = 0; r < RH; ++r)
+#pragma unroll
+        for (int q = 0; q < QP; ++q) acc[r] = fma(lf[g][q], yv[g][r][q], acc[r]);
+  }
+#pragma unroll
+  for (int r = 0; r < RH; ++r) {
+    const double s = red8(acc[r]);
+    if (r < S.nrhs && p == r) astore<double>(S.z + ((int64_t)B * S.nrhs + r) * SB + i, s);
   }
   return true;
 }
@@ -409,24 +427,26 @@ __global__ void __launch_bounds__(NT) solve_kernel(SolveArgs S) {
     } else {
       // forward: B = ST+1 .. NB-1; back: B = NB-ST-2 .. 0
       const int B = FWD ? ST + t : S.NB - ST - 1 - t;
-      if (!helper<ST, FWD>(S, B, (lds_i*)&s_flag)) break;
+      const bool ok = S.nrhs == 1 ? helper<ST, FWD, 2, 1>(S, B, (lds_i*)&s_flag)
+                                  : helper<ST, FWD, 1, RHS_MAX>(S, B, (lds_i*)&s_flag);
+      if (!ok) break;
     }
     if (s_flag) break;
   }
 }
 
 // Fills the first len elements of the 4 publication buffers (stride apart)
-// with the unset pattern, zeroes the counters and sets the zero element.
+// with the unset pattern, zeroes the counters and sets the QP zeros.
 __global__ void solve_fill_kernel(glb_d* p, int64_t len, int64_t stride, unsigned* queues, glb_i* abort_flag,
                                   glb_d* zero) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t x = g; x < 4 * len; x += (int64_t)gridDim.x * blockDim.x)
     p[(x / len) * stride + x % len] = __longlong_as_double(UNSET);
+  if (g < QP) zero[g] = 0.0;
   if (g == 0) {
     queues[0] = 0;
     queues[1] = 0;
     *abort_flag = 0;
-    *zero = 0.0;
   }
 }
 
@@ -561,8 +581,8 @@ inline int blocks_of_band(int64_t n, int64_t k) {
 }  // namespace bandchol_solve
 
 // Host side, called by the C-ABI (same library).  Workspace layout, in bytes
-// from `ws`: [0,256) two ticket counters, the abort flag, (at 64) the zero
-// element and (at 128) the sink; then the publication area, 4 * RHS_MAX * NBT
+// from `ws`: [0,256) two ticket counters, the abort flag, (at 64) QP zeros
+// and (at 128) the sink; then the publication area, 4 * RHS_MAX * NBT
 // doubles (forward result, back result, forward and back helper sums, RHS_MAX
 // * NBT each, of which a pass of nrhs right-hand sides uses the first
 // nrhs * NBT); then the inverted tiles, 2 * NB * T * T doubles; then the
