@@ -91,6 +91,17 @@ __device__ __forceinline__ float prec_sqrt(float x) { return sqrtf(x); }
 // stores) have completed.
 __device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
+// The pointer p, hidden from the optimiser (an empty register constraint, no
+// instruction): a load from a select between an element and a stand-in is
+// otherwise turned into a branch around the load, and the branch makes the
+// wave wait for loads still in flight.
+template <typename P>
+__device__ __forceinline__ P opaque_ptr(P p) {
+  uint64_t u = (uint64_t)p;
+  asm("" : "+v"(u));
+  return (P)u;
+}
+
 // Relaxed agent-scope atomic accesses: coherent across the chip's L2 caches
 // without cache maintenance; used for data that other workgroups read.
 template <typename F>

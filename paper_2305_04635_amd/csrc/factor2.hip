@@ -42,6 +42,7 @@ struct Ws {
   unsigned* queue;
   glb_i* abort_flag;  // 1 = pivot failure, 2 = wait bound exceeded
   unsigned long long* first_fail;
+  const glb_t<F>* zero;  // a zero: masked-off lanes load it, so that operand loads are unconditional
 };
 
 template <typename F>
@@ -123,18 +124,21 @@ __device__ __forceinline__ void wblk_store(glb_t<F>* t, int bi, int bj, v4_t<F> 
 
 // acc -= X_blk(bi) Y_blk(bj)^T with X = tile (Rx, s), Y = tile (Ry, s) from the band.
 template <typename F>
-__device__ __forceinline__ v4_t<F> aterm(const BandT<F>& a, int64_t Rx, int64_t Ry, int64_t s, int bi, int bj,
-                                         v4_t<F> acc) {
+__device__ __forceinline__ void term_load(const Args<F>& A, int64_t Rx, int64_t Ry, int64_t s, int bi, int bj,
+                                          F (&xf)[T / 4], F (&yf)[T / 4]) {
   const int lane = lane_id();
   const int64_t j0 = s * T + (lane >> 4);
-  const RunT<F> x = band_run(a, Rx * T + 16 * bi + (lane & 15), j0, 4);
-  const RunT<F> y = band_run(a, Ry * T + 16 * bj + (lane & 15), j0, 4);
-  F xf[T / 4], yf[T / 4];
+  const RunT<F> x = band_run(A.a, Rx * T + 16 * bi + (lane & 15), j0, 4);
+  const RunT<F> y = band_run(A.a, Ry * T + 16 * bj + (lane & 15), j0, 4);
 #pragma unroll
   for (int q = 0; q < T / 4; ++q) {
-    xf[q] = x.ald(q);
-    yf[q] = y.ald(q);
+    xf[q] = aload<F>(opaque_ptr(x.in(q) ? x.at(q) : A.w.zero));
+    yf[q] = aload<F>(opaque_ptr(y.in(q) ? y.at(q) : A.w.zero));
   }
+}
+
+template <typename F>
+__device__ __forceinline__ v4_t<F> term_apply(const F (&xf)[T / 4], const F (&yf)[T / 4], v4_t<F> acc) {
 #pragma unroll
   for (int q = 0; q < T / 4; ++q) acc = mfma_xyt(-xf[q], yf[q], acc);
   return acc;
@@ -142,16 +146,45 @@ __device__ __forceinline__ v4_t<F> aterm(const BandT<F>& a, int64_t Rx, int64_t 
 
 // ---------------------------------------------------------------- helpers
 
-// Apply the terms s in [s0, s1) of tile (R, C) (blocks of this wave), in runs
-// of published operand tiles.  Xrow = R, Yrow = C.
+// Apply the terms s in [s0, s1) of tile (R, C) (blocks of this wave):
+// acc -= L(R,s) L(C,s)^T.  The flags of up to 16 terms are read at once (for a
+// fixed tile row they are contiguous, one per lane); within a run of
+// published terms the operands of the next term load while the current one
+// is on the matrix cores, both steps of each pair always taken (the last term
+// of the run stands in past its end) so that the wave's counter of
+// outstanding loads stays exact.  Xrow = R, Yrow = C.
 template <typename F>
 __device__ __forceinline__ bool apply_terms(const Args<F>& A, int64_t R, int64_t C, int64_t s0, int64_t s1, int bi, int bj,
                                             v4_t<F>& acc) {
-  for (int64_t s = s0; s < s1; ++s) {
-    // operands: tile (R, s) and tile (C, s); spine tiles (d = 1) and helper tiles share one flag array
-    if (!wave_wait(&A.w.tflag[tidx(A, R, s)], A.w)) return false;
-    if (C != R && !wave_wait(&A.w.tflag[tidx(A, C, s)], A.w)) return false;
-    acc = aterm(A.a, R, C, s, bi, bj, acc);
+  const int lane = lane_id();
+  int64_t s = s0;
+  while (s < s1) {
+    const int span = s1 - s < 16 ? (int)(s1 - s) : 16;
+    int f = 1;
+    if (lane < span) {
+      f = __hip_atomic_load(&A.w.tflag[tidx(A, R, s + lane)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (C != R) f &= __hip_atomic_load(&A.w.tflag[tidx(A, C, s + lane)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const unsigned long long bad = __ballot(lane < span && f == 0);
+    int64_t e = s + (bad ? (int)__builtin_ctzll(bad) : span);
+    if (e == s) {
+      if (!wave_wait(&A.w.tflag[tidx(A, R, s)], A.w)) return false;
+      if (C != R && !wave_wait(&A.w.tflag[tidx(A, C, s)], A.w)) return false;
+      e = s + 1;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");  // keeps the operand loads below the flags
+    F x0[T / 4], y0[T / 4], x1[T / 4], y1[T / 4];
+    term_load(A, R, C, s, bi, bj, x0, y0);
+    term_load(A, R, C, s + 1 < e ? s + 1 : e - 1, bi, bj, x1, y1);
+    int64_t u = s;
+    for (; u + 1 < e; u += 2) {
+      acc = term_apply(x0, y0, acc);
+      term_load(A, R, C, u + 2 < e ? u + 2 : e - 1, bi, bj, x0, y0);
+      acc = term_apply(x1, y1, acc);
+      term_load(A, R, C, u + 3 < e ? u + 3 : e - 1, bi, bj, x1, y1);
+    }
+    if (u < e) acc = term_apply(x0, y0, acc);
+    s = e;
   }
   return true;
 }
@@ -213,13 +246,34 @@ __device__ __attribute__((noinline)) void task_pre(const Args<F>& A_, int64_t m,
   v4_t<F> acc = ablk_load(A.a, m, m - 1, bi, bj);
   v4_t<F> accd = {0, 0, 0, 0};
   if (wave >= 1) accd = ablk_load(A.a, m, m, di, dj);
-  for (int64_t s = s0; s < m - 2; ++s) {
-    if (!wave_wait(&A.w.tflag[tidx(A, m, s)], A.w) || !wave_wait(&A.w.tflag[tidx(A, m - 1, s)], A.w)) {
-      ok = 0;
-      break;
+  const int lane = lane_id();
+  int64_t s = s0;
+  while (ok && s < m - 2) {
+    // flags of up to 16 terms at once (rows m and m-1), as in apply_terms
+    const int span = m - 2 - s < 16 ? (int)(m - 2 - s) : 16;
+    int f = 1;
+    if (lane < span)
+      f = __hip_atomic_load(&A.w.tflag[tidx(A, m, s + lane)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+          __hip_atomic_load(&A.w.tflag[tidx(A, m - 1, s + lane)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long bad = __ballot(lane < span && f == 0);
+    int64_t e = s + (bad ? (int)__builtin_ctzll(bad) : span);
+    if (e == s) {
+      if (!wave_wait(&A.w.tflag[tidx(A, m, s)], A.w) || !wave_wait(&A.w.tflag[tidx(A, m - 1, s)], A.w)) {
+        ok = 0;
+        break;
+      }
+      e = s + 1;
     }
-    acc = aterm(A.a, m, m - 1, s, bi, bj, acc);
-    if (wave >= 1) accd = aterm(A.a, m, m, s, di, dj, accd);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");  // keeps the operand loads below the flags
+    for (; s < e; ++s) {
+      F xf[T / 4], yf[T / 4];
+      term_load(A, m, m - 1, s, bi, bj, xf, yf);
+      acc = term_apply(xf, yf, acc);
+      if (wave >= 1) {
+        term_load(A, m, m, s, di, dj, xf, yf);
+        accd = term_apply(xf, yf, accd);
+      }
+    }
   }
   wblk_store(po, bi, bj, acc);
   if (wave >= 1) wblk_store(pd, di, dj, accd);
@@ -514,10 +568,11 @@ __global__ void __launch_bounds__(NT, 2) factor2_kernel(Args<F> A) {
   }
 }
 
-__global__ void factor2_init(glb_i* flags, int64_t count, unsigned* queue, glb_i* abort_flag, unsigned long long* ff) {
+__global__ void factor2_init(glb_i* flags, int64_t count, unsigned* queue, glb_i* abort_flag, unsigned long long* ff,
+                             unsigned long long* zero) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t x = g; x < count; x += (int64_t)gridDim.x * blockDim.x) flags[x] = 0;
-  if (g == 0) { *queue = 0; *abort_flag = 0; *ff = 0x7fffffffffffffffULL; }
+  if (g == 0) { *queue = 0; *abort_flag = 0; *ff = 0x7fffffffffffffffULL; *zero = 0; }
 }
 
 __global__ void factor2_finish(const glb_i* abort_flag, const unsigned long long* ff, int64_t* d_info) {
@@ -554,6 +609,7 @@ static hipError_t factor2_launch(int64_t n, int64_t k, F* ab, int64_t ldab, int6
   A.w.queue = (unsigned*)base;
   A.w.abort_flag = (glb_i*)(base + 8);
   A.w.first_fail = (unsigned long long*)(base + 16);
+  A.w.zero = (const glb_t<F>*)(base + 64);
   A.w.tflag = (glb_i*)(base + 256);
   A.w.hflag = A.w.tflag + (size_t)NB * (K + 1);
   const size_t flags = sizeof(int) * (size_t)(NB * (K + 1) + NB);
@@ -562,7 +618,7 @@ static hipError_t factor2_launch(int64_t n, int64_t k, F* ab, int64_t ldab, int6
   A.ntickets = 1 + tickets_per_column(K) * (unsigned)NB;
   const int64_t nflags = (int64_t)NB * (K + 1) + NB;
   factor2_init<<<(unsigned)((nflags + 255) / 256 > 1024 ? 1024 : (nflags + 255) / 256 + 1), 256, 0, st>>>(
-      A.w.tflag, nflags, A.w.queue, A.w.abort_flag, A.w.first_fail);
+      A.w.tflag, nflags, A.w.queue, A.w.abort_flag, A.w.first_fail, (unsigned long long*)(base + 64));
   int grid = grid_max;
   if ((unsigned)grid > A.ntickets) grid = (int)A.ntickets;
   factor2_kernel<F><<<grid, NT, 0, st>>>(A);
