@@ -98,8 +98,10 @@ int64_t bandchol_tile(void);
  * Tuning: single matrices whose band spans at most `kmax` sub-diagonal tiles
  * (k <= kmax * bandchol_tile()) are factored by one workgroup walking the band;
  * wider bands use the multi-workgroup tile schedule.  kmax is clamped to
- * [0, 15].  Returns the previous limit; a negative kmax only queries it.
- * Process-wide; not synchronised with calls running in other threads.
+ * [0, 15]; the default is 0 (only diagonal matrices walk).  Returns the
+ * previous limit; a negative kmax only queries it.  Process-wide; not
+ * synchronised with calls running in other threads.  Batch plans always walk
+ * systems of up to 15 tile diagonals.
  */
 int64_t bandchol_set_walk_limit(int64_t kmax);
 

@@ -166,7 +166,7 @@ int num_cus() {
 int g_walk_kmax = -1;
 int walk_kmax() {
   if (g_walk_kmax < 0) {
-    g_walk_kmax = 2;
+    g_walk_kmax = 0;   // the spine schedule is faster for a single matrix from K = 1 on
     if (const char* e = getenv("BANDCHOL_WALK_KMAX")) g_walk_kmax = (int)strtol(e, nullptr, 10);
     if (g_walk_kmax > WALK_KMAX) g_walk_kmax = WALK_KMAX;
   }
