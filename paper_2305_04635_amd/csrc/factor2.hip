@@ -137,6 +137,15 @@ __device__ __forceinline__ void term_load(const Args<F>& A, int64_t Rx, int64_t 
   }
 }
 
+// Only the X operand (block bi of tile (Rx, s)).
+template <typename F>
+__device__ __forceinline__ void term_load_x(const Args<F>& A, int64_t Rx, int64_t s, int bi, F (&xf)[T / 4]) {
+  const int lane = lane_id();
+  const RunT<F> x = band_run(A.a, Rx * T + 16 * bi + (lane & 15), s * T + (lane >> 4), 4);
+#pragma unroll
+  for (int q = 0; q < T / 4; ++q) xf[q] = aload<F>(opaque_ptr(x.in(q) ? x.at(q) : A.w.zero));
+}
+
 template <typename F>
 __device__ __forceinline__ v4_t<F> term_apply(const F (&xf)[T / 4], const F (&yf)[T / 4], v4_t<F> acc) {
 #pragma unroll
@@ -227,6 +236,87 @@ __device__ __attribute__((noinline)) void task_off(const Args<F>& A_, int64_t R,
   wait_vmem();
   __syncthreads();
   if (threadIdx.x == 0) raise_flag(&A.w.tflag[tidx(A, R, C)]);
+}
+
+// Two tiles of one column: (R, C) and (R+1, C) share the operand L(C, s) of
+// every term, so a term loads three blocks for two outputs and puts twice the
+// matrix-core work behind each round trip.  When R > K the first term,
+// s = R-K, lies outside the band of row R+1: that operand loads as zero and
+// its flag is not checked.  Same run structure as apply_terms.
+template <typename F>
+__device__ __forceinline__ bool apply_terms2(const Args<F>& A, int64_t R, int64_t C, int64_t s0, int64_t s1, int bi,
+                                             int bj, v4_t<F>& acc0, v4_t<F>& acc1) {
+  const int lane = lane_id();
+  const int64_t s_in1 = R + 1 - A.K;   // first term inside the band for row R+1
+  int64_t s = s0;
+  while (s < s1) {
+    const int span = s1 - s < 16 ? (int)(s1 - s) : 16;
+    int f = 1;
+    if (lane < span) {
+      const int64_t u = s + lane;
+      f = __hip_atomic_load(&A.w.tflag[tidx(A, R, u)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+          __hip_atomic_load(&A.w.tflag[tidx(A, C, u)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (u >= s_in1) f &= __hip_atomic_load(&A.w.tflag[tidx(A, R + 1, u)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const unsigned long long bad = __ballot(lane < span && f == 0);
+    int64_t e = s + (bad ? (int)__builtin_ctzll(bad) : span);
+    if (e == s) {
+      if (!wave_wait(&A.w.tflag[tidx(A, R, s)], A.w) || !wave_wait(&A.w.tflag[tidx(A, C, s)], A.w)) return false;
+      if (s >= s_in1 && !wave_wait(&A.w.tflag[tidx(A, R + 1, s)], A.w)) return false;
+      e = s + 1;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");  // keeps the operand loads below the flags
+    F a0[T / 4], b0[T / 4], y0[T / 4], a1[T / 4], b1[T / 4], y1[T / 4];
+    term_load(A, R, C, s, bi, bj, a0, y0);
+    term_load_x(A, R + 1, s, bi, b0);
+    term_load(A, R, C, s + 1 < e ? s + 1 : e - 1, bi, bj, a1, y1);
+    term_load_x(A, R + 1, s + 1 < e ? s + 1 : e - 1, bi, b1);
+    int64_t u = s;
+    for (; u + 1 < e; u += 2) {
+      acc0 = term_apply(a0, y0, acc0);
+      acc1 = term_apply(b0, y0, acc1);
+      term_load(A, R, C, u + 2 < e ? u + 2 : e - 1, bi, bj, a0, y0);
+      term_load_x(A, R + 1, u + 2 < e ? u + 2 : e - 1, bi, b0);
+      acc0 = term_apply(a1, y1, acc0);
+      acc1 = term_apply(b1, y1, acc1);
+      term_load(A, R, C, u + 3 < e ? u + 3 : e - 1, bi, bj, a1, y1);
+      term_load_x(A, R + 1, u + 3 < e ? u + 3 : e - 1, bi, b1);
+    }
+    if (u < e) {
+      acc0 = term_apply(a0, y0, acc0);
+      acc1 = term_apply(b0, y0, acc1);
+    }
+    s = e;
+  }
+  return true;
+}
+
+template <typename F>
+__device__ __attribute__((noinline)) void task_off2(const Args<F>& A_, int64_t R, int64_t C, lds_t<F>* stage,
+                                                    lds_i* s_ok) {
+  const Args<F> A = A_;
+  const int wave = wave_id();
+  const int bi = wave & 1, bj = wave >> 1;
+  v4_t<F> acc0 = ablk_load(A.a, R, C, bi, bj);
+  v4_t<F> acc1 = ablk_load(A.a, R + 1, C, bi, bj);
+  const int64_t s0 = R - A.K > 0 ? R - A.K : 0;
+  int ok = apply_terms2(A, R, C, s0, C, bi, bj, acc0, acc1) ? 1 : 0;
+  if (ok) ok = wave_wait(&A.w.tflag[tidx(A, C, C)], A.w) ? 1 : 0;
+  blk_to_lds(stage, bi, bj, acc0);
+  blk_to_lds(stage + T * LP, bi, bj, acc1);
+  if (!ok && lane_id() == 0) *s_ok = 0;
+  __syncthreads();
+  if (*s_ok == 0) return;
+  const v4_t<F> out0 = trsm_from_lds<F>(stage, A.w.linvt + C * T * T, bi, bj);
+  const v4_t<F> out1 = trsm_from_lds<F>(stage + T * LP, A.w.linvt + C * T * T, bi, bj);
+  ablk_store(A.a, R, C, bi, bj, out0);
+  ablk_store(A.a, R + 1, C, bi, bj, out1);
+  wait_vmem();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    raise_flag(&A.w.tflag[tidx(A, R, C)]);
+    raise_flag(&A.w.tflag[tidx(A, R + 1, C)]);
+  }
 }
 
 // Pre-accumulate the spine's tiles of step m-1: (m, m-1) and (m, m), terms s <= m-3.
@@ -517,20 +607,27 @@ __device__ void spine(const Args<F>& A, lds_t<F>* base, lds_i* s_fail, lds_i* s_
 
 // ---------------------------------------------------------------- kernel
 
-// Ticket order: 0 = spine; then per column C: O(C+2..C+K, C), then H(C+3).
+// Ticket order: 0 = spine; then per column C: O(C+2, C) alone (the spine
+// waits on it), O(C+3..C+K, C) in pairs (the last one alone when K is even),
+// then H(C+3).
+__host__ __device__ __forceinline__ unsigned off_tasks(int K) { return K >= 2 ? 1u + (unsigned)(K - 1) / 2u : 0u; }
 __host__ __device__ __forceinline__ unsigned tickets_per_column(int K) {
-  return K >= 2 ? (unsigned)(K - 1) + (K >= 3 ? 1u : 0u) : 0u;
+  return K >= 2 ? off_tasks(K) + (K >= 3 ? 1u : 0u) : 0u;
 }
 
+// kind 1: tile (R, C); kind 3: tiles (R, C) and (R+1, C); kind 2: H(R).
 template <typename F>
 __device__ __forceinline__ void decode(const Args<F>& A, unsigned t, int& kind, int64_t& R, int64_t& C) {
   const unsigned per = tickets_per_column(A.K);
   const unsigned u = t - 1;
   C = u / per;
   const unsigned slot = u % per;
-  if (slot < (unsigned)(A.K - 1)) {
+  if (slot == 0) {
     kind = 1;
-    R = C + 2 + slot;
+    R = C + 2;
+  } else if (slot < off_tasks(A.K)) {
+    R = C + 3 + 2 * (slot - 1);
+    kind = (R + 1 <= C + A.K && R + 1 < A.NB) ? 3 : 1;
   } else {
     kind = 2;
     R = C + 3;
@@ -561,6 +658,7 @@ __global__ void __launch_bounds__(NT, 2) factor2_kernel(Args<F> A) {
       decode(A, t, kind, R, C);
       if (R < A.NB) {
         if (kind == 1) task_off<F>(A, R, C, (lds_t<F>*)lds, (lds_i*)&s_ok);
+        else if (kind == 3) task_off2<F>(A, R, C, (lds_t<F>*)lds, (lds_i*)&s_ok);
         else task_pre(A, R, (lds_i*)&s_ok);
       }
     }
