@@ -300,8 +300,13 @@ __device__ __forceinline__ void sweep_half(F (&row)[T], int j0, F& dcur, F& d_mi
   }
 }
 
-template <typename F>
-__device__ __forceinline__ int sweep_ldlt(F (&row)[T], lds_t<F>* sq, lds_t<F>* sd) {
+struct NoHook {
+  __device__ void operator()() const {}
+};
+
+// `mid` runs between the two halves (a point some microseconds into the sweep).
+template <typename F, typename Hook = NoHook>
+__device__ __forceinline__ int sweep_ldlt(F (&row)[T], lds_t<F>* sq, lds_t<F>* sd, Hook mid = Hook()) {
   const int lane = lane_id();
   constexpr int H = T / 2;
   constexpr int QP = 2 * T + 1;           // LDS pitch of a column over the 64 lanes
@@ -334,6 +339,7 @@ __device__ __forceinline__ int sweep_ldlt(F (&row)[T], lds_t<F>* sq, lds_t<F>* s
       sq[(Prec<F>::acc_col0(lane) + Prec<F>::ACC_STEP * r) * QP + 16 * b + (lane & 15)] = acc[b][r];
 #pragma unroll
   for (int c = 0; c < H; ++c) row[H + c] -= sq[c * QP + lane];
+  mid();
   dcur = readlane(row[H], H);
   sweep_half(row, H, dcur, d_mine, fail);
   const F s_mine = prec_sqrt(d_mine);

@@ -3,19 +3,23 @@
 //
 // Tiles T x T down the band, tile (R, C) for 0 <= R - C <= K.  One workgroup,
 // the spine (whoever takes ticket 0), carries the dependency chain along the
-// diagonal, one tile column per step:
+// diagonal and the first two sub-diagonals, one tile column per step C:
 //   phase A  wave 0: factor the staged diagonal tile (register sweep) ->
-//            L(C,C) and L(C,C)^{-T}, published at once;
-//            waves 1-3: complete tile (C+1, C) and the next diagonal tile with
-//            the one term (column C-1) the helpers could not have applied yet;
-//   phase B  all waves: L(C+1, C) = tile * L(C,C)^{-T}, published;
-//   phase C  waves 1-3: next diagonal tile -= L(C+1,C) L(C+1,C)^T, staged.
+//            L(C,C) and L(C,C)^{-T}, stored at once;
+//            waves 1-3: L(C+1, C-1) from its pre-accumulated sum, the terms
+//            s = C-3, C-2 and the previous step's L(C-1,C-1)^{-T}; then tile
+//            (C+1, C) and the next diagonal tile with the terms s = C-2, C-1;
+//   phase B  all waves: L(C+1, C) = tile * L(C,C)^{-T};
+//   phase C  waves 0, 2, 3: next diagonal tile -= L(C+1,C) L(C+1,C)^T, staged.
 // Helper workgroups take the other tickets, in an order where every task only
 // waits for lower tickets or for spine steps:
-//   O(R, C), R - C >= 2: acc = A(R,C) - sum_s L(R,s) L(C,s)^T (terms applied as
+//   O(R, C), R - C >= 3: acc = A(R,C) - sum_s L(R,s) L(C,s)^T (terms applied as
 //            their operand tiles are published), then L(R,C) = acc L(C,C)^{-T};
-//   H(m):    the spine's two tiles of step m-1, (m, m-1) and (m, m), with every
-//            term but the last one (s <= m-3) applied, published for the spine.
+//            two tiles of one column share a task;
+//   H(m):    the row-m tiles the spine completes, (m, m-1) and (m, m) at step
+//            m-1 and (m+1, m-1) at step m, summed over s <= m-4.
+// Whatever the spine takes from a helper depends only on spine results at
+// least two steps old, so the helpers' round trips stay off its chain.
 // Data between workgroups moves through relaxed agent-scope atomic loads and
 // stores (coherent across the chip without cache flushes); a flag is raised
 // after the data stores of the raising wave(s) have completed.
@@ -37,8 +41,8 @@ template <typename F>
 struct Ws {
   glb_i* tflag;     // NB*(K+1): tile (R, R-d) published, index R*(K+1)+d
   glb_i* hflag;     // NB: pre-accumulated tiles of step m-1 published
-  glb_t<F>* linvt;  // NB*T*T: L(C,C)^{-T}, row-major
-  glb_t<F>* pre;    // NB*2*T*T: per m, tile (m,m-1) then tile (m,m), column-major
+  glb_t<F>* linvt;  // NB*T*T: L(C,C)^{-T}, column-major
+  glb_t<F>* pre;    // NB*3*T*T: per m, tiles (m,m-1), (m,m), (m+1,m-1), column-major
   unsigned* queue;
   glb_i* abort_flag;  // 1 = pivot failure, 2 = wait bound exceeded
   unsigned long long* first_fail;
@@ -198,7 +202,8 @@ __device__ __forceinline__ bool apply_terms(const Args<F>& A, int64_t R, int64_t
   return true;
 }
 
-// Trsm of the accumulator tile held across the 4 waves: out = acc * L(C,C)^{-T}.
+// Trsm of the accumulator tile held across the 4 waves: out = acc * L(C,C)^{-T}
+// (L^{-T} column-major in global memory).
 template <typename F>
 __device__ __forceinline__ v4_t<F> trsm_from_lds(const lds_t<F>* x, const glb_t<F>* linvt_g, int bi, int bj) {
   const int lane = lane_id();
@@ -207,7 +212,7 @@ __device__ __forceinline__ v4_t<F> trsm_from_lds(const lds_t<F>* x, const glb_t<
   F yf[T / 4];
 #pragma unroll
   for (int q = 0; q < T / 4; ++q)
-    yf[q] = (q < qmax) ? aload<F>(linvt_g + (4 * q + (lane >> 4)) * T + 16 * bj + (lane & 15)) : F(0);
+    yf[q] = (q < qmax) ? aload<F>(linvt_g + (16 * bj + (lane & 15)) * T + 4 * q + (lane >> 4)) : F(0);
 #pragma unroll
   for (int q = 0; q < T / 4; ++q)
     if (q < qmax) out = mfma_xyt(x[(4 * q + (lane >> 4)) * LP + 16 * bi + (lane & 15)], yf[q], out);
@@ -319,36 +324,48 @@ __device__ __attribute__((noinline)) void task_off2(const Args<F>& A_, int64_t R
   }
 }
 
-// Pre-accumulate the spine's tiles of step m-1: (m, m-1) and (m, m), terms s <= m-3.
+// H(m): the row-m tiles the spine completes, summed over the terms s <= m-4:
+// (m, m-1) and (m, m), taken at step m-1, and (m+1, m-1), taken at step m.
+// Each wave takes one block of (m, m-1) and of (m+1, m-1) (both use the block
+// bj of L(m-1, s)); waves 1-3 also one lower block of (m, m).  Terms are
+// applied as their operands are published.
 template <typename F>
 __device__ __attribute__((noinline)) void task_pre(const Args<F>& A_, int64_t m, lds_i* s_ok) {
   const Args<F> A = A_;
   const int wave = wave_id();
+  const int lane = lane_id();
+  const bool third = m + 1 < A.NB;
   const int64_t s0 = m - A.K > 0 ? m - A.K : 0;
-  glb_t<F>* po = A.w.pre + m * 2 * T * T;
+  const int64_t s0p = m + 1 - A.K;  // row m+1 enters the band at this column
+  const int64_t s1 = m - 3;
+  glb_t<F>* po = A.w.pre + m * 3 * T * T;
   glb_t<F>* pd = po + T * T;
-  // waves 0-3: one block of (m, m-1) each; waves 1-3 also one lower block of
-  // (m, m).  Both blocks of a wave take each term as soon as its operands are
-  // published, so that only the last term is left once the last one arrives.
-  int ok = 1;
+  glb_t<F>* pp = pd + T * T;
   const int bi = wave & 1, bj = wave >> 1;
   const int di = (wave >= 2), dj = (wave == 3);
   v4_t<F> acc = ablk_load(A.a, m, m - 1, bi, bj);
+  v4_t<F> accp = {0, 0, 0, 0};
+  if (third) accp = ablk_load(A.a, m + 1, m - 1, bi, bj);
   v4_t<F> accd = {0, 0, 0, 0};
   if (wave >= 1) accd = ablk_load(A.a, m, m, di, dj);
-  const int lane = lane_id();
+  int ok = 1;
   int64_t s = s0;
-  while (ok && s < m - 2) {
-    // flags of up to 16 terms at once (rows m and m-1), as in apply_terms
-    const int span = m - 2 - s < 16 ? (int)(m - 2 - s) : 16;
+  while (ok && s < s1) {
+    // flags of up to 16 terms at once, as in apply_terms
+    const int span = s1 - s < 16 ? (int)(s1 - s) : 16;
     int f = 1;
-    if (lane < span)
-      f = __hip_atomic_load(&A.w.tflag[tidx(A, m, s + lane)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
-          __hip_atomic_load(&A.w.tflag[tidx(A, m - 1, s + lane)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (lane < span) {
+      const int64_t u = s + lane;
+      f = __hip_atomic_load(&A.w.tflag[tidx(A, m, u)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+          __hip_atomic_load(&A.w.tflag[tidx(A, m - 1, u)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (third && u >= s0p)
+        f &= __hip_atomic_load(&A.w.tflag[tidx(A, m + 1, u)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     const unsigned long long bad = __ballot(lane < span && f == 0);
     int64_t e = s + (bad ? (int)__builtin_ctzll(bad) : span);
     if (e == s) {
-      if (!wave_wait(&A.w.tflag[tidx(A, m, s)], A.w) || !wave_wait(&A.w.tflag[tidx(A, m - 1, s)], A.w)) {
+      if (!wave_wait(&A.w.tflag[tidx(A, m, s)], A.w) || !wave_wait(&A.w.tflag[tidx(A, m - 1, s)], A.w) ||
+          (third && s >= s0p && !wave_wait(&A.w.tflag[tidx(A, m + 1, s)], A.w))) {
         ok = 0;
         break;
       }
@@ -359,6 +376,10 @@ __device__ __attribute__((noinline)) void task_pre(const Args<F>& A_, int64_t m,
       F xf[T / 4], yf[T / 4];
       term_load(A, m, m - 1, s, bi, bj, xf, yf);
       acc = term_apply(xf, yf, acc);
+      if (third) {
+        term_load_x(A, m + 1, s, bi, xf);  // zero while row m+1 is outside the band
+        accp = term_apply(xf, yf, accp);
+      }
       if (wave >= 1) {
         term_load(A, m, m, s, di, dj, xf, yf);
         accd = term_apply(xf, yf, accd);
@@ -366,6 +387,7 @@ __device__ __attribute__((noinline)) void task_pre(const Args<F>& A_, int64_t m,
     }
   }
   wblk_store(po, bi, bj, acc);
+  if (third) wblk_store(pp, bi, bj, accp);
   if (wave >= 1) wblk_store(pd, di, dj, accd);
   if (!ok && lane_id() == 0) *s_ok = 0;
   wait_vmem();
@@ -378,35 +400,54 @@ __device__ __attribute__((noinline)) void task_pre(const Args<F>& A_, int64_t m,
 
 template <typename F>
 struct SpineLds {
-  lds_t<F>* diag;    // staged diagonal tile (column-major, LP)
-  lds_t<F>* acco;    // staged tile (C+1, C)
-  lds_t<F>* accd;    // next diagonal tile before its last update
-  lds_t<F>* lcur;    // L(C+1, C)
-  lds_t<F>* lprev;   // L(C, C-1)
-  lds_t<F>* linvt;   // L(C,C)^{-T}, row-major, row pitch LP
-  lds_t<F>* lcc;     // L(C,C) (column-major, LP)
-  lds_t<F>* linvt_prev;   // the same two of the previous step, being published
-  lds_t<F>* lcc_prev;
+  lds_t<F>* diag;        // staged diagonal tile D(C) (column-major, LP); scratch of the sweep
+  lds_t<F>* sd;          // T/2 pivots, scratch of the sweep
+  lds_t<F>* linvt;       // L(C,C)^{-T}, row-major, row pitch LP
+  lds_t<F>* linvt_prev;  // L(C-1,C-1)^{-T}
+  lds_t<F>* acco;        // tile (C+1, C) before its trsm
+  lds_t<F>* accd;        // tile (C+1, C+1) before its last term
+  lds_t<F>* lcur;        // L(C+1, C) from phase B; in phase A the staged tile (C+1, C-1)
+  lds_t<F>* lprev;       // L(C, C-1)
+  lds_t<F>* l2cur;       // L(C+1, C-1)
+  lds_t<F>* l2prev;      // L(C, C-2)
 };
 
-// Wave 0: the sweep of the staged diagonal tile; L(C,C) and L(C,C)^{-T} go to
-// LDS only (both conflict-free: pitch LP); another wave copies them to global
-// memory off the critical path.  Takes only scalars and LDS pointers (no
-// structures): a structure passed to a noinline function is read back from the
-// stack, a memory round trip at the head of the chain.
+// Wave 0: the sweep of the staged diagonal tile D(C); L(C,C) replaces the
+// tile in its LDS buffer (column-major, pitch LP) and L(C,C)^{-T} goes to
+// `linvt` (row-major, pitch LP).  On entry the previous step's inverse,
+// `linvt_prev`, is copied to `lt_prev` (column-major: store p covers elements
+// 64p .. 64p+63), and between the two halves of the sweep, once those stores
+// have long completed, `flag_prev` is raised: the helpers' trsm takes
+// L(C-1,C-1)^{-T} from there.
 template <typename F>
-__device__ __attribute__((noinline)) void spine_sweep(lds_t<F>* diag, lds_t<F>* lcc, lds_t<F>* linvt, int64_t col0,
-                                                      int64_t n, unsigned long long* first_fail, glb_i* abort_flag,
+__device__ __forceinline__ void spine_sweep(lds_t<F>* diag, lds_t<F>* sd, lds_t<F>* linvt,
+                                                      const lds_t<F>* linvt_prev, glb_t<F>* lt_prev,
+                                                      glb_i* flag_prev, int64_t C, int64_t n,
+                                                      unsigned long long* first_fail, glb_i* abort_flag,
                                                       lds_i* s_fail) {
   const int lane = lane_id();
+  if (flag_prev) {
+    const int r = lane & 31, h = lane >> 5;
+    F v[T / 2];
+#pragma unroll
+    for (int p = 0; p < T / 2; ++p) v[p] = linvt_prev[r * LP + 2 * p + h];  // element (r, 2p + h)
+#pragma unroll
+    for (int p = 0; p < T / 2; ++p) astore(lt_prev + 64 * p + lane, v[p]);
+  }
   F row[T];
 #pragma unroll
   for (int c = 0; c < T; ++c) row[c] = lane < T ? diag[c * LP + lane] : ((lane - T) == c ? F(1) : F(0));
-  const int fail = sweep_ldlt(row, diag, lcc);  // both free while this wave sweeps
+  auto mid = [flag_prev, lane]() {
+    if (flag_prev) {
+      wait_vmem();
+      if (lane == 0) raise_flag(flag_prev);
+    }
+  };
+  const int fail = sweep_ldlt(row, diag, sd, mid);  // the tile is in registers: its LDS is scratch
   if (fail >= 0) {
     if (lane == 0) {
       *s_fail = fail;
-      const long long col = (long long)col0 + fail;
+      const long long col = (long long)C * T + fail;
       if (col < n) atomicMin(first_fail, (unsigned long long)(col + 1));
       __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -414,206 +455,323 @@ __device__ __attribute__((noinline)) void spine_sweep(lds_t<F>* diag, lds_t<F>* 
   }
 #pragma unroll
   for (int c = 0; c < T; ++c) {
-    if (lane < T) lcc[c * LP + lane] = row[c];
+    if (lane < T) diag[c * LP + lane] = row[c];
     else linvt[(lane - T) * LP + c] = row[c];
   }
 }
 
-// Waves 1-3 copy the spine's results of step C from LDS to global memory with
-// coalesced stores, one part each: wave 1 L(C,C) (lower triangle, from `lcc`),
-// wave 2 L(C,C)^{-T} (row-major, for the helpers' trsm, from `linvt`), wave 3
-// L(C+1, C) from `lcur` (if `off`).  Does not wait for them.
+// L(C,C) from LDS (column-major, pitch LP) to the band, lower triangle: lane
+// (r, h) stores column 2p + h of row r.  Not waited for; four values at a
+// time keep the registers it needs inside the kernel few.
 template <typename F>
-__device__ __attribute__((noinline)) void spine_publish(const Args<F>& A_, int64_t C, const lds_t<F>* lcc,
-                                                        const lds_t<F>* linvt, const lds_t<F>* lcur, bool off,
-                                                        int part) {
-  const Args<F> A = A_;
-  const BandT<F>& a = A.a;
+__device__ __forceinline__ void store_lcc(const lds_t<F>* lcc, int64_t C, const BandT<F>& a) {
   const int lane = lane_id();
-  const int r = lane & 31;
-  // all LDS reads first, then the stores (a store waiting on its own read
-  // would serialise the LDS latency)
-  F v[T / 2];
-  if (part == 1) {
+  const int r = lane & 31, h = lane >> 5;
+  const RunT<F> rd = band_run(a, C * T + r, C * T + h, 2);
+#pragma unroll 1
+  for (int p0 = 0; p0 < T / 2; p0 += 4) {
+    F v[4];
 #pragma unroll
-    for (int p = 0; p < T / 2; ++p) v[p] = lcc[(2 * p + (lane >> 5)) * LP + r];
-    // lane (r, h) stores column 2p + h of row r
-    const RunT<F> rd = band_run(a, C * T + r, C * T + (lane >> 5), 2);
+    for (int p = 0; p < 4; ++p) v[p] = lcc[(2 * (p0 + p) + h) * LP + r];
 #pragma unroll
-    for (int p = 0; p < T / 2; ++p)
-      if (rd.in(p)) astore(rd.at(p), v[p]);
-  } else if (part == 2) {
-    glb_t<F>* lt = A.w.linvt + C * T * T;
-#pragma unroll
-    for (int p = 0; p < T / 2; ++p) {
-      const int e = 64 * p + lane;
-      v[p] = linvt[(e / T) * LP + (e % T)];
-    }
-#pragma unroll
-    for (int p = 0; p < T / 2; ++p) astore(lt + 64 * p + lane, v[p]);
-  } else if (part == 3 && off) {
-#pragma unroll
-    for (int p = 0; p < T / 2; ++p) v[p] = lcur[(2 * p + (lane >> 5)) * LP + r];
-    const RunT<F> ro = band_run(a, (C + 1) * T + r, C * T + (lane >> 5), 2);
-#pragma unroll
-    for (int p = 0; p < T / 2; ++p)
-      if (ro.in(p)) astore(ro.at(p), v[p]);
+    for (int p = 0; p < 4; ++p)
+      if (rd.in(p0 + p)) astore(rd.at(p0 + p), v[p]);
   }
 }
 
-// waves 1-3: tiles (C+1, C) and (C+1, C+1) with everything but the critical
-// update.  The 7 lower blocks (4 of (m, C), 3 of (m, m)) go to waves 2 and 3
-// three each (b = 0, 2, 4 and 1, 3, 5) and to wave 1 one (b = 6), since wave 1
-// also publishes a third of the previous step.  The term s = C-1 uses X = L(m, C-1) for both
-// tiles, Y = L(C, C-1) (staged in LDS) for (m, C) and Y = L(m, C-1) for (m, m);
-// every global load is issued before the first MFMA.
+// Workgroup barrier for LDS data only: unlike __syncthreads it does not wait
+// for this wave's global stores, which only other workgroups read (after a
+// flag raised once they have drained).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// Up to three flags (null: none) polled in one round trip; bounded like wave_wait.
 template <typename F>
-__device__ __attribute__((noinline)) void spine_prepare(const Args<F>& A_, int64_t C, const SpineLds<F>& S_,
-                                                        lds_i* s_fail) {
-  const Args<F> A = A_;
-  const SpineLds<F> S = S_;
+__device__ __forceinline__ bool wave_wait3(const glb_i* f0, const glb_i* f1, const glb_i* f2, const Ws<F>& w) {
+  const int lane = lane_id();
+  const glb_i* mine = lane == 0 ? f0 : lane == 1 ? f1 : lane == 2 ? f2 : nullptr;
+  long long spins = 0;
+  for (;;) {
+    int v = 1;
+    if (mine) v = __hip_atomic_load(mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (__ballot(v == 0) == 0) break;
+    if (aflag(w.abort_flag)) return false;
+    if (++spins > SPIN_LIMIT) {
+      __hip_atomic_store(w.abort_flag, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  return true;
+}
+
+// Flags between waves 1-3 inside phase A, where wave 0 is sweeping and no
+// workgroup barrier can be used.  A wave's LDS accesses reach the LDS in
+// order, so a flag written after a wave's data is seen after that data.
+__device__ __forceinline__ void lds_signal(lds_i* f, int v) {
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  if (lane_id() == 0) __hip_atomic_store(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ bool lds_wait(lds_i* f, int v) {
+  int spins = 0;
+  while (__builtin_amdgcn_readfirstlane(__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) < v) {
+    if (++spins > (1 << 24)) return false;
+    __builtin_amdgcn_s_sleep(0);
+  }
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  return true;
+}
+
+// Waves 1-3 in phase A of step C (m = C+1), alongside the sweep:
+//   * publication of the previous step: wave 1 stores wave 0's block of
+//     L(C, C-1) from LDS (after its own loads, which would otherwise wait for
+//     that store); at the end each wave drains its stores and counts in, and
+//     the third raises the flags of L(C, C-1) and L(C, C-2);
+//   * tile (m, C-1): the helpers' sum over s <= C-4, here the terms s = C-3
+//     and C-2, then L(m, C-1) = tile L(C-1,C-1)^{-T} (the previous sweep's
+//     inverse, still in LDS); row half h on wave 1+h;
+//   * tiles (m, C) and (m, m): the helpers' sums over s <= C-3; here s = C-2
+//     (wave 3, all blocks), then s = C-1 with the new L(m, C-1) (waves 1 and 2
+//     their row half, wave 3 block (1, 0) of (m, m)).
+template <typename F>
+__device__ __forceinline__ void spine_prepare(const Args<F>& A, int64_t C, const SpineLds<F>& S, bool next,
+                                              lds_i* sync, lds_i* s_pub, lds_i* s_fail) {
   const int wave = wave_id();
   const int lane = lane_id();
+  const int K = A.K;
   const int64_t m = C + 1;
-  const bool have_pre = A.K >= 3 && m >= 3;
-  const glb_t<F>* po = A.w.pre + m * 2 * T * T;
-  const glb_t<F>* pd = po + T * T;
-  if (have_pre && !wave_wait(&A.w.hflag[m], A.w)) { if (lane == 0) *s_fail = -2; return; }
-  // term s = C-1 needs L(m, C-1) (a helper tile) and L(C, C-1) (S.lprev)
-  const bool t1 = C >= 1 && A.K >= 2;
-  if (t1 && !wave_wait(&A.w.tflag[tidx(A, m, C - 1)], A.w)) { if (lane == 0) *s_fail = -2; return; }
-  v4_t<F> acc[3];
-  F x0[T / 4], x1[T / 4];  // fragments of L(m, C-1), rows 0-15 and 16-31
+  const bool copy0 = C >= 1 && K >= 1;  // wave 1 stores wave 0's block of L(C, C-1)
+  if (next) {
+    const bool pre_o = K >= 4 && m >= 4;  // (m, C), (m, m) from H(m)
+    const bool pre_p = K >= 4 && C >= 4;  // (m, C-1) from H(C)
+    const bool has_p = K >= 2 && C >= 1;  // tile (m, C-1) is inside the band
+    const bool t2 = K >= 3 && C >= 2;     // term s = C-2: L(m, C-2)
+    const bool t3 = K >= 4 && C >= 3;     // term s = C-3 of (m, C-1): L(m, C-3)
+    const int tag = (int)C + 1;
+    bool ok = wave_wait3(pre_o ? &A.w.hflag[m] : nullptr, t2 ? &A.w.tflag[tidx(A, m, C - 2)] : nullptr,
+                         t3 ? &A.w.tflag[tidx(A, m, C - 3)] : nullptr, A.w);
+    if (wave == 3) {
+      const glb_t<F>* po = A.w.pre + m * 3 * T * T;
+      v4_t<F> acc[7];  // blocks 0-3: (m, C), b -> (b & 1, b >> 1); 4-6: (m, m), (0,0) (1,0) (1,1)
+      F x3[2][T / 4];
 #pragma unroll
-  for (int u = 0; u < 3; ++u) {
-    const int b = wave == 1 ? (u == 0 ? 6 : 7) : wave - 2 + 2 * u;
-    acc[u] = v4_t<F>{0, 0, 0, 0};
-    if (b < 4) {
-      const int bi = b & 1, bj = b >> 1;
-      acc[u] = have_pre ? wblk_load(po, bi, bj) : ablk_load(A.a, m, C, bi, bj);
-    } else if (b < 7) {
-      const int bi = (b >= 5), bj = (b == 6);
-      acc[u] = have_pre ? wblk_load(pd, bi, bj) : ablk_load(A.a, m, m, bi, bj);
-    }
-  }
-  if (t1) {
-    const int64_t j0 = (C - 1) * T + (lane >> 4);
-    const RunT<F> r0 = band_run(A.a, m * T + (lane & 15), j0, 4);
-    const RunT<F> r1 = band_run(A.a, m * T + 16 + (lane & 15), j0, 4);
-#pragma unroll
-    for (int q = 0; q < T / 4; ++q) {
-      x0[q] = r0.ald(q);
-      x1[q] = r1.ald(q);
-    }
-  }
-#pragma unroll
-  for (int u = 0; u < 3; ++u) {
-    const int b = wave == 1 ? (u == 0 ? 6 : 7) : wave - 2 + 2 * u;
-    if (b < 4) {
-      const int bi = b & 1, bj = b >> 1;
-      if (t1) {
-#pragma unroll
-        for (int q = 0; q < T / 4; ++q)
-          acc[u] = mfma_xyt(-(bi ? x1[q] : x0[q]), S.lprev[(4 * q + (lane >> 4)) * LP + 16 * bj + (lane & 15)], acc[u]);
+      for (int b = 0; b < 7; ++b) {
+        const int bi = b < 4 ? (b & 1) : (b >= 5), bj = b < 4 ? (b >> 1) : (b == 6);
+        if (pre_o) acc[b] = wblk_load(po + (b < 4 ? 0 : T * T), bi, bj);
+        else acc[b] = ablk_load(A.a, m, b < 4 ? C : m, bi, bj);
       }
-      blk_to_lds(S.acco, bi, bj, acc[u]);
-    } else if (b < 7) {
-      const int bi = (b >= 5), bj = (b == 6);
-      if (t1) {
+      if (t2) {
+        term_load_x(A, m, C - 2, 0, x3[0]);
+        term_load_x(A, m, C - 2, 1, x3[1]);
 #pragma unroll
-        for (int q = 0; q < T / 4; ++q) acc[u] = mfma_xyt(-(bi ? x1[q] : x0[q]), bj ? x1[q] : x0[q], acc[u]);
+        for (int b = 0; b < 7; ++b) {
+          const int bi = b < 4 ? (b & 1) : (b >= 5), bj = b < 4 ? (b >> 1) : (b == 6);
+#pragma unroll
+          for (int q = 0; q < T / 4; ++q) {
+            const F y = b < 4 ? S.l2prev[(4 * q + (lane >> 4)) * LP + 16 * bj + (lane & 15)] : x3[bj][q];
+            acc[b] = mfma_xyt(-x3[bi][q], y, acc[b]);
+          }
+        }
       }
-      blk_to_lds(S.accd, bi, bj, acc[u]);
+#pragma unroll
+      for (int b = 0; b < 7; ++b) {
+        const int bi = b < 4 ? (b & 1) : (b >= 5), bj = b < 4 ? (b >> 1) : (b == 6);
+        blk_to_lds(b < 4 ? S.acco : S.accd, bi, bj, acc[b]);
+      }
+      lds_signal(&sync[2], tag);
+      if (has_p) {
+        if (!lds_wait(&sync[0], tag) || !lds_wait(&sync[1], tag)) {
+          ok = false;
+        } else {
+          v4_t<F> v = blk_from_lds<F>(S.accd, 1, 0);
+          v = blk_gemm_lds<F>(S.l2cur, S.l2cur, 1, 0, v);
+          blk_to_lds(S.accd, 1, 0, v);
+        }
+      }
+    } else {
+      const int h = wave - 1;
+      if (has_p) {
+        v4_t<F> pp[2];
+        F x3[T / 4], x4[T / 4], y1[2][T / 4], y2[2][T / 4];
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+          pp[bj] = pre_p ? wblk_load(A.w.pre + C * 3 * T * T + 2 * T * T, h, bj) : ablk_load(A.a, m, C - 1, h, bj);
+        if (t2) {
+          term_load_x(A, m, C - 2, h, x3);
+          term_load_x(A, C - 1, C - 2, 0, y1[0]);
+          term_load_x(A, C - 1, C - 2, 1, y1[1]);
+        }
+        if (t3) {
+          term_load_x(A, m, C - 3, h, x4);
+          term_load_x(A, C - 1, C - 3, 0, y2[0]);
+          term_load_x(A, C - 1, C - 3, 1, y2[1]);
+        }
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+          if (t3) pp[bj] = term_apply(x4, y2[bj], pp[bj]);
+          if (t2) pp[bj] = term_apply(x3, y1[bj], pp[bj]);
+          blk_to_lds(S.lcur, h, bj, pp[bj]);
+        }
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+          const v4_t<F> out = blk_trsm_lds<F>(S.lcur, S.linvt_prev, h, bj, LP);
+          blk_to_lds(S.l2cur, h, bj, out);
+          ablk_store(A.a, m, C - 1, h, bj, out);
+        }
+      }
+      if (wave == 1 && copy0) ablk_store(A.a, C, C - 1, 0, 0, blk_from_lds<F>(S.lprev, 0, 0));
+      lds_signal(&sync[h], tag);
+      if (!lds_wait(&sync[2], tag)) {
+        ok = false;
+      } else if (has_p) {
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+          v4_t<F> v = blk_from_lds<F>(S.acco, h, bj);
+          v = blk_gemm_lds<F>(S.l2cur, S.lprev, h, bj, v);
+          blk_to_lds(S.acco, h, bj, v);
+        }
+        v4_t<F> v = blk_from_lds<F>(S.accd, h, h);
+        v = blk_gemm_lds<F>(S.l2cur, S.l2cur, h, h, v);
+        blk_to_lds(S.accd, h, h, v);
+      }
+    }
+    if (!ok && lane == 0) *s_fail = -2;
+  } else if (wave == 1 && copy0) {
+    ablk_store(A.a, C, C - 1, 0, 0, blk_from_lds<F>(S.lprev, 0, 0));
+  }
+  wait_vmem();
+  if (C >= 1 && lane == 0) {
+    const int before = __hip_atomic_fetch_add(s_pub, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (before == 3 * (int)C - 1) {
+      if (K >= 1) raise_flag(&A.w.tflag[tidx(A, C, C - 1)]);
+      if (K >= 2 && C >= 2) raise_flag(&A.w.tflag[tidx(A, C, C - 2)]);
     }
   }
 }
 
+// The spine's steps, one function for wave 0 and one for waves 1-3, each
+// called once: no call inside the step loop (a call makes the loop's live
+// values spill, and their reloads wait for every store in flight), and the
+// kernel's registers, allocated for the helper tasks, stay out of it.  Both
+// pass the same three barriers per step.
 template <typename F>
-__device__ void spine(const Args<F>& A, lds_t<F>* base, lds_i* s_fail, lds_i* s_pub) {
-  const int wave = wave_id();
+__device__ __attribute__((noinline)) void spine_wave0(const Args<F>& A_, const SpineLds<F>& S_, lds_i* s_fail) {
+  const Args<F> A = A_;
+  SpineLds<F> S = S_;
   const BandT<F>& a = A.a;
+  for (int64_t C = 0; C < A.NB; ++C) {
+    const bool next = C + 1 < A.NB;
+    // phase A
+    spine_sweep<F>(S.diag, S.sd, S.linvt, S.linvt_prev, A.w.linvt + (C - 1) * T * T,
+                   C >= 1 ? &A.w.tflag[tidx(A, C - 1, C - 1)] : nullptr, C, a.n, A.w.first_fail, A.w.abort_flag,
+                   s_fail);
+    lds_barrier();
+    if (*s_fail != -1 || !next) return;
+    // phase B: block (0, 0) of L(C+1, C) = acco * L(C,C)^{-T}; wave 1 stores it
+    // during the next step
+    if (A.K >= 1) blk_to_lds(S.lcur, 0, 0, blk_trsm_lds(S.acco, S.linvt, 0, 0, LP));
+    lds_barrier();
+    // phase C: block (0, 0) of the next diagonal tile, staged in acco's buffer
+    v4_t<F> acc = blk_from_lds<F>(S.accd, 0, 0);
+    if (A.K >= 1) acc = blk_gemm_lds<F>(S.lcur, S.lcur, 0, 0, acc);
+    blk_to_lds<F>(S.acco, 0, 0, acc);
+    blk_to_lds<F>(S.acco, 0, 1, v4_t<F>{0, 0, 0, 0});
+    lds_t<F>* t = S.diag; S.diag = S.acco; S.acco = t;
+    t = S.lprev; S.lprev = S.lcur; S.lcur = t;
+    t = S.l2prev; S.l2prev = S.l2cur; S.l2cur = t;
+    t = S.linvt_prev; S.linvt_prev = S.linvt; S.linvt = t;
+    lds_barrier();
+  }
+}
+
+template <typename F>
+__device__ __attribute__((noinline)) void spine_waves123(const Args<F>& A_, const SpineLds<F>& S_, lds_i* sync,
+                                                         lds_i* s_pub, lds_i* s_fail) {
+  const Args<F> A = A_;
+  SpineLds<F> S = S_;
+  const BandT<F>& a = A.a;
+  const int wave = wave_id();
+  for (int64_t C = 0; C < A.NB; ++C) {
+    const bool next = C + 1 < A.NB;
+    // phase A
+    spine_prepare(A, C, S, next, sync, s_pub, s_fail);
+    lds_barrier();
+    if (*s_fail != -1) return;
+    if (!next) {
+      if (wave == 1) store_lcc(S.diag, C, a);
+      return;
+    }
+    // phase B: L(C+1, C) = acco * L(C,C)^{-T}, one block per wave, stored now
+    if (A.K >= 1) {
+      const int bi = wave & 1, bj = wave >> 1;
+      const v4_t<F> v = blk_trsm_lds(S.acco, S.linvt, bi, bj, LP);
+      blk_to_lds(S.lcur, bi, bj, v);
+      ablk_store(a, C + 1, C, bi, bj, v);
+    }
+    lds_barrier();
+    // phase C: blocks (1,0), (1,1) of the next diagonal tile on waves 2, 3,
+    // staged in acco's buffer; wave 1 stores L(C,C), which stays in the
+    // diagonal tile's buffer until the rotation
+    if (wave >= 2) {
+      const int bi = 1, bj = (wave == 3);
+      v4_t<F> acc = blk_from_lds<F>(S.accd, bi, bj);
+      if (A.K >= 1) acc = blk_gemm_lds<F>(S.lcur, S.lcur, bi, bj, acc);
+      blk_to_lds<F>(S.acco, bi, bj, acc);
+    } else {
+      store_lcc(S.diag, C, a);
+    }
+    lds_t<F>* t = S.diag; S.diag = S.acco; S.acco = t;
+    t = S.lprev; S.lprev = S.lcur; S.lcur = t;
+    t = S.l2prev; S.l2prev = S.l2cur; S.l2cur = t;
+    t = S.linvt_prev; S.linvt_prev = S.linvt; S.linvt = t;
+    lds_barrier();
+  }
+}
+
+template <typename F>
+__device__ void spine(const Args<F>& A, lds_t<F>* base, lds_i* s_fail, lds_i* s_pub, lds_i* sync) {
+  const int wave = wave_id();
   SpineLds<F> S;
   S.diag = base;
-  S.acco = S.diag + T * LP;
+  S.linvt = S.diag + T * LP;
+  S.linvt_prev = S.linvt + T * LP;
+  S.acco = S.linvt_prev + T * LP;
   S.accd = S.acco + T * LP;
   S.lcur = S.accd + T * LP;
   S.lprev = S.lcur + T * LP;
-  S.linvt = S.lprev + T * LP;
-  S.lcc = S.linvt + T * LP;
-  S.linvt_prev = S.lcc + T * LP;
-  S.lcc_prev = S.linvt_prev + T * LP;
+  S.l2cur = S.lprev + T * LP;
+  S.l2prev = S.l2cur + T * LP;
+  S.sd = S.l2prev + T * LP;
   if (threadIdx.x == 0) {
     *s_fail = -1;
     *s_pub = 0;
+    sync[0] = sync[1] = sync[2] = 0;
   }
   // stage tile (0,0)
   if (wave >= 1) {
     const int bi = (wave >= 2), bj = (wave == 3);
-    blk_to_lds(S.diag, bi, bj, ablk_load(a, 0, 0, bi, bj));
+    blk_to_lds(S.diag, bi, bj, ablk_load(A.a, 0, 0, bi, bj));
   } else {
     blk_to_lds(S.diag, 0, 1, v4_t<F>{0, 0, 0, 0});
   }
-  __syncthreads();
-  for (int64_t C = 0; C < A.NB; ++C) {
-    const bool next = C + 1 < A.NB;
-    // waves 1-3 publish step C-1 (its L(C-1,C-1) and inverse sit in the
-    // previous-step buffers, L(C,C-1) in lprev) while wave 0 already sweeps
-    // step C; each drains its own stores and counts in; the third raises the
-    // flags (the prepare below waits, through a helper task, on them)
-    if (wave >= 1 && C >= 1) {
-      spine_publish(A, C - 1, S.lcc_prev, S.linvt_prev, S.lprev, A.K >= 1, wave);
-      wait_vmem();
-      if (lane_id() == 0) {
-        const int before = __hip_atomic_fetch_add(s_pub, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (before == 3 * (int)C - 1) {
-          raise_flag(&A.w.tflag[tidx(A, C - 1, C - 1)]);
-          if (A.K >= 1) raise_flag(&A.w.tflag[tidx(A, C, C - 1)]);
-        }
-      }
-    }
-    // phase A
-    if (wave == 0) spine_sweep<F>(S.diag, S.lcc, S.linvt, C * T, A.a.n, A.w.first_fail, A.w.abort_flag, s_fail);
-    else if (next && A.K >= 1) spine_prepare(A, C, S, s_fail);
-    else if (next && wave >= 1) {
-      const int bi = (wave >= 2), bj = (wave == 3);
-      blk_to_lds(S.accd, bi, bj, ablk_load(a, C + 1, C + 1, bi, bj));
-    }
-    __syncthreads();
-    if (*s_fail != -1) return;
-    if (!next) {
-      if (wave >= 1) spine_publish(A, C, S.lcc, S.linvt, S.lcur, false, wave);
-      return;
-    }
-    // phase B: L(C+1, C) = acco * L(C,C)^{-T}, into LDS
-    if (A.K >= 1) {
-      const int bi = wave & 1, bj = wave >> 1;
-      blk_to_lds(S.lcur, bi, bj, blk_trsm_lds(S.acco, S.linvt, bi, bj, LP));
-    }
-    __syncthreads();
-    // phase C: next diagonal tile (blocks (0,0), (1,0), (1,1) on waves 0, 2, 3)
-    if (wave != 1) {
-      const int bi = (wave >= 2), bj = (wave == 3);
-      v4_t<F> acc = blk_from_lds<F>(S.accd, bi, bj);
-      if (A.K >= 1) acc = blk_gemm_lds<F>(S.lcur, S.lcur, bi, bj, acc);
-      blk_to_lds<F>(S.diag, bi, bj, acc);
-      if (wave == 0) blk_to_lds<F>(S.diag, 0, 1, v4_t<F>{0, 0, 0, 0});
-    }
-    lds_t<F>* t = S.lprev; S.lprev = S.lcur; S.lcur = t;
-    t = S.lcc_prev; S.lcc_prev = S.lcc; S.lcc = t;
-    t = S.linvt_prev; S.linvt_prev = S.linvt; S.linvt = t;
-    __syncthreads();
-  }
+  lds_barrier();
+  if (wave == 0) spine_wave0(A, S, s_fail);
+  else spine_waves123(A, S, sync, s_pub, s_fail);
 }
 
 // ---------------------------------------------------------------- kernel
 
-// Ticket order: 0 = spine; then per column C: O(C+2, C) alone (the spine
-// waits on it), O(C+3..C+K, C) in pairs (the last one alone when K is even),
-// then H(C+3).
-__host__ __device__ __forceinline__ unsigned off_tasks(int K) { return K >= 2 ? 1u + (unsigned)(K - 1) / 2u : 0u; }
-__host__ __device__ __forceinline__ unsigned tickets_per_column(int K) {
-  return K >= 2 ? off_tasks(K) + (K >= 3 ? 1u : 0u) : 0u;
-}
+// Ticket order: 0 = spine; then per column C the tiles O(C+3..C+K, C) in
+// pairs (the last one alone when their count is odd), with H(C+4) after the
+// first two pairs (its last terms use the tiles of those pairs).
+__host__ __device__ __forceinline__ unsigned off_pairs(int K) { return K >= 3 ? (unsigned)(K - 1) / 2u : 0u; }
+__host__ __device__ __forceinline__ unsigned tickets_per_column(int K) { return off_pairs(K) + (K >= 4 ? 1u : 0u); }
 
 // kind 1: tile (R, C); kind 3: tiles (R, C) and (R+1, C); kind 2: H(R).
 template <typename F>
@@ -621,23 +779,25 @@ __device__ __forceinline__ void decode(const Args<F>& A, unsigned t, int& kind, 
   const unsigned per = tickets_per_column(A.K);
   const unsigned u = t - 1;
   C = u / per;
-  const unsigned slot = u % per;
-  if (slot == 0) {
-    kind = 1;
-    R = C + 2;
-  } else if (slot < off_tasks(A.K)) {
-    R = C + 3 + 2 * (slot - 1);
-    kind = (R + 1 <= C + A.K && R + 1 < A.NB) ? 3 : 1;
-  } else {
-    kind = 2;
-    R = C + 3;
+  unsigned slot = u % per;
+  const unsigned np = off_pairs(A.K);
+  const unsigned hs = np < 2u ? np : 2u;
+  if (A.K >= 4) {
+    if (slot == hs) {
+      kind = 2;
+      R = C + 4;
+      return;
+    }
+    if (slot > hs) --slot;
   }
+  R = C + 3 + 2 * (int64_t)slot;
+  kind = (R + 1 <= C + A.K && R + 1 < A.NB) ? 3 : 1;
 }
 
 template <typename F>
 __global__ void __launch_bounds__(NT, 2) factor2_kernel(Args<F> A) {
-  __shared__ F lds[9 * T * LP];
-  __shared__ int s_ticket, s_ok, s_abort, s_pub;
+  __shared__ F lds[9 * T * LP + T / 2];
+  __shared__ int s_ticket, s_ok, s_abort, s_pub, s_sync[3];
   for (;;) {
     if (threadIdx.x == 0) {
       s_ticket = (int)atomicAdd(A.w.queue, 1u);
@@ -651,7 +811,7 @@ __global__ void __launch_bounds__(NT, 2) factor2_kernel(Args<F> A) {
     __syncthreads();
     if (t >= A.ntickets || stop) break;
     if (t == 0) {
-      spine<F>(A, (lds_t<F>*)lds, (lds_i*)&s_ok, (lds_i*)&s_pub);
+      spine<F>(A, (lds_t<F>*)lds, (lds_i*)&s_ok, (lds_i*)&s_pub, (lds_i*)s_sync);
     } else {
       int kind;
       int64_t R, C;
@@ -686,7 +846,7 @@ static size_t factor2_workspace(int64_t n, int64_t K, size_t elem) {
   using namespace bandchol_f2;
   const int64_t NB = (n + T - 1) / T;
   const size_t flags = sizeof(int) * (size_t)(NB * (K + 1) + NB);
-  return 256 + ((flags + 255) & ~(size_t)255) + elem * (size_t)NB * T * T * 3;
+  return 256 + ((flags + 255) & ~(size_t)255) + elem * (size_t)NB * T * T * 4;
 }
 
 size_t bandchol_factor2_workspace(int64_t n, int64_t K) { return factor2_workspace(n, K, sizeof(double)); }
