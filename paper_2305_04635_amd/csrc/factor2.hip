@@ -16,8 +16,10 @@
 //   O(R, C), R - C >= 3: acc = A(R,C) - sum_s L(R,s) L(C,s)^T (terms applied as
 //            their operand tiles are published), then L(R,C) = acc L(C,C)^{-T};
 //            two tiles of one column share a task;
-//   H(m):    the row-m tiles the spine completes, (m, m-1) and (m, m) at step
-//            m-1 and (m+1, m-1) at step m, summed over s <= m-4.
+//   H(m):    the tiles (m, m-1) and (m, m) the spine completes at step m-1,
+//            summed over s <= m-4;
+//   P(m):    the tile (m, m-2) the spine completes at step m-1, summed over
+//            s <= m-5.
 // Whatever the spine takes from a helper depends only on spine results at
 // least two steps old, so the helpers' round trips stay off its chain.
 // Data between workgroups moves through relaxed agent-scope atomic loads and
@@ -40,9 +42,10 @@ constexpr long long SPIN_LIMIT = 1LL << 22;
 template <typename F>
 struct Ws {
   glb_i* tflag;     // NB*(K+1): tile (R, R-d) published, index R*(K+1)+d
-  glb_i* hflag;     // NB: pre-accumulated tiles of step m-1 published
+  glb_i* hflag;     // NB: H(m) published
+  glb_i* pflag;     // NB: P(m) published
   glb_t<F>* linvt;  // NB*T*T: L(C,C)^{-T}, column-major
-  glb_t<F>* pre;    // NB*3*T*T: per m, tiles (m,m-1), (m,m), (m+1,m-1), column-major
+  glb_t<F>* pre;    // NB*3*T*T: per m, tiles (m,m-1), (m,m) (from H(m)), (m+1,m-1) (from P(m+1)), column-major
   unsigned* queue;
   glb_i* abort_flag;  // 1 = pivot failure, 2 = wait bound exceeded
   unsigned long long* first_fail;
@@ -324,76 +327,104 @@ __device__ __attribute__((noinline)) void task_off2(const Args<F>& A_, int64_t R
   }
 }
 
-// H(m): the row-m tiles the spine completes, summed over the terms s <= m-4:
-// (m, m-1) and (m, m), taken at step m-1, and (m+1, m-1), taken at step m.
-// Each wave takes one block of (m, m-1) and of (m+1, m-1) (both use the block
-// bj of L(m-1, s)); waves 1-3 also one lower block of (m, m).  Terms are
-// applied as their operands are published.
+// H(m): the tiles (m, m-1) and (m, m) the spine completes at step m-1, summed
+// over the terms s <= m-4.  Each wave takes one block of (m, m-1) and one of
+// (m, m) (waves 1-3 the three lower ones; wave 0 repeats block (0, 0) and
+// drops it); every wave loads both row halves of L(m, s) and one of L(m-1, s),
+// so that all issue the same loads.  Terms are applied in runs of published
+// operands, the next term's operands loading while the current one is on the
+// matrix cores, as in apply_terms.
+template <typename F>
+struct PreOps {
+  F x0[T / 4], x1[T / 4], y[T / 4];  // L(m, s) both row halves, L(m-1, s) half bj
+};
+
+template <typename F>
+__device__ __forceinline__ void pre_load(const Args<F>& A, int64_t m, int64_t s, int bj, PreOps<F>& o) {
+  term_load(A, m, m - 1, s, 0, bj, o.x0, o.y);
+  term_load_x(A, m, s, 1, o.x1);
+}
+
+template <typename F>
+__device__ __forceinline__ void pre_apply(const PreOps<F>& o, bool bi, bool di, bool dj, v4_t<F>& acc,
+                                          v4_t<F>& accd) {
+#pragma unroll
+  for (int q = 0; q < T / 4; ++q) {
+    acc = mfma_xyt(-(bi ? o.x1[q] : o.x0[q]), o.y[q], acc);
+    accd = mfma_xyt(-(di ? o.x1[q] : o.x0[q]), dj ? o.x1[q] : o.x0[q], accd);
+  }
+}
+
 template <typename F>
 __device__ __attribute__((noinline)) void task_pre(const Args<F>& A_, int64_t m, lds_i* s_ok) {
   const Args<F> A = A_;
   const int wave = wave_id();
   const int lane = lane_id();
-  const bool third = m + 1 < A.NB;
   const int64_t s0 = m - A.K > 0 ? m - A.K : 0;
-  const int64_t s0p = m + 1 - A.K;  // row m+1 enters the band at this column
   const int64_t s1 = m - 3;
   glb_t<F>* po = A.w.pre + m * 3 * T * T;
   glb_t<F>* pd = po + T * T;
-  glb_t<F>* pp = pd + T * T;
   const int bi = wave & 1, bj = wave >> 1;
   const int di = (wave >= 2), dj = (wave == 3);
   v4_t<F> acc = ablk_load(A.a, m, m - 1, bi, bj);
-  v4_t<F> accp = {0, 0, 0, 0};
-  if (third) accp = ablk_load(A.a, m + 1, m - 1, bi, bj);
-  v4_t<F> accd = {0, 0, 0, 0};
-  if (wave >= 1) accd = ablk_load(A.a, m, m, di, dj);
+  v4_t<F> accd = ablk_load(A.a, m, m, di, dj);
   int ok = 1;
   int64_t s = s0;
-  while (ok && s < s1) {
+  while (s < s1) {
     // flags of up to 16 terms at once, as in apply_terms
     const int span = s1 - s < 16 ? (int)(s1 - s) : 16;
     int f = 1;
-    if (lane < span) {
-      const int64_t u = s + lane;
-      f = __hip_atomic_load(&A.w.tflag[tidx(A, m, u)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
-          __hip_atomic_load(&A.w.tflag[tidx(A, m - 1, u)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (third && u >= s0p)
-        f &= __hip_atomic_load(&A.w.tflag[tidx(A, m + 1, u)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    if (lane < span)
+      f = __hip_atomic_load(&A.w.tflag[tidx(A, m, s + lane)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+          __hip_atomic_load(&A.w.tflag[tidx(A, m - 1, s + lane)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const unsigned long long bad = __ballot(lane < span && f == 0);
     int64_t e = s + (bad ? (int)__builtin_ctzll(bad) : span);
     if (e == s) {
-      if (!wave_wait(&A.w.tflag[tidx(A, m, s)], A.w) || !wave_wait(&A.w.tflag[tidx(A, m - 1, s)], A.w) ||
-          (third && s >= s0p && !wave_wait(&A.w.tflag[tidx(A, m + 1, s)], A.w))) {
+      if (!wave_wait(&A.w.tflag[tidx(A, m, s)], A.w) || !wave_wait(&A.w.tflag[tidx(A, m - 1, s)], A.w)) {
         ok = 0;
         break;
       }
       e = s + 1;
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");  // keeps the operand loads below the flags
-    for (; s < e; ++s) {
-      F xf[T / 4], yf[T / 4];
-      term_load(A, m, m - 1, s, bi, bj, xf, yf);
-      acc = term_apply(xf, yf, acc);
-      if (third) {
-        term_load_x(A, m + 1, s, bi, xf);  // zero while row m+1 is outside the band
-        accp = term_apply(xf, yf, accp);
-      }
-      if (wave >= 1) {
-        term_load(A, m, m, s, di, dj, xf, yf);
-        accd = term_apply(xf, yf, accd);
-      }
+    PreOps<F> o0, o1;
+    pre_load(A, m, s, bj, o0);
+    pre_load(A, m, s + 1 < e ? s + 1 : e - 1, bj, o1);
+    int64_t u = s;
+    for (; u + 1 < e; u += 2) {
+      pre_apply(o0, bi, di, dj, acc, accd);
+      pre_load(A, m, u + 2 < e ? u + 2 : e - 1, bj, o0);
+      pre_apply(o1, bi, di, dj, acc, accd);
+      pre_load(A, m, u + 3 < e ? u + 3 : e - 1, bj, o1);
     }
+    if (u < e) pre_apply(o0, bi, di, dj, acc, accd);
+    s = e;
   }
   wblk_store(po, bi, bj, acc);
-  if (third) wblk_store(pp, bi, bj, accp);
   if (wave >= 1) wblk_store(pd, di, dj, accd);
   if (!ok && lane_id() == 0) *s_ok = 0;
   wait_vmem();
   __syncthreads();
   if (*s_ok == 0) return;
   if (threadIdx.x == 0) raise_flag(&A.w.hflag[m]);
+}
+
+// P(m): the tile (m, m-2) the spine completes at step m-1, summed over the
+// terms s <= m-5, into the workspace slot of row m-1.
+template <typename F>
+__device__ __attribute__((noinline)) void task_p(const Args<F>& A_, int64_t m, lds_i* s_ok) {
+  const Args<F> A = A_;
+  const int wave = wave_id();
+  const int bi = wave & 1, bj = wave >> 1;
+  v4_t<F> acc = ablk_load(A.a, m, m - 2, bi, bj);
+  const int64_t s0 = m - A.K > 0 ? m - A.K : 0;
+  const int ok = apply_terms(A, m, m - 2, s0, m - 4, bi, bj, acc) ? 1 : 0;
+  wblk_store(A.w.pre + (m - 1) * 3 * T * T + 2 * T * T, bi, bj, acc);
+  if (!ok && lane_id() == 0) *s_ok = 0;
+  wait_vmem();
+  __syncthreads();
+  if (*s_ok == 0) return;
+  if (threadIdx.x == 0) raise_flag(&A.w.pflag[m]);
 }
 
 // ---------------------------------------------------------------- spine
@@ -489,11 +520,12 @@ __device__ __forceinline__ void lds_barrier() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-// Up to three flags (null: none) polled in one round trip; bounded like wave_wait.
+// Up to four flags (null: none) polled in one round trip; bounded like wave_wait.
 template <typename F>
-__device__ __forceinline__ bool wave_wait3(const glb_i* f0, const glb_i* f1, const glb_i* f2, const Ws<F>& w) {
+__device__ __forceinline__ bool wave_wait4(const glb_i* f0, const glb_i* f1, const glb_i* f2, const glb_i* f3,
+                                           const Ws<F>& w) {
   const int lane = lane_id();
-  const glb_i* mine = lane == 0 ? f0 : lane == 1 ? f1 : lane == 2 ? f2 : nullptr;
+  const glb_i* mine = lane == 0 ? f0 : lane == 1 ? f1 : lane == 2 ? f2 : lane == 3 ? f3 : nullptr;
   long long spins = 0;
   for (;;) {
     int v = 1;
@@ -549,13 +581,14 @@ __device__ __forceinline__ void spine_prepare(const Args<F>& A, int64_t C, const
   const bool copy0 = C >= 1 && K >= 1;  // wave 1 stores wave 0's block of L(C, C-1)
   if (next) {
     const bool pre_o = K >= 4 && m >= 4;  // (m, C), (m, m) from H(m)
-    const bool pre_p = K >= 4 && C >= 4;  // (m, C-1) from H(C)
+    const bool pre_p = K >= 5 && C >= 4;  // (m, C-1) from P(m)
     const bool has_p = K >= 2 && C >= 1;  // tile (m, C-1) is inside the band
     const bool t2 = K >= 3 && C >= 2;     // term s = C-2: L(m, C-2)
     const bool t3 = K >= 4 && C >= 3;     // term s = C-3 of (m, C-1): L(m, C-3)
     const int tag = (int)C + 1;
-    bool ok = wave_wait3(pre_o ? &A.w.hflag[m] : nullptr, t2 ? &A.w.tflag[tidx(A, m, C - 2)] : nullptr,
-                         t3 ? &A.w.tflag[tidx(A, m, C - 3)] : nullptr, A.w);
+    bool ok = wave_wait4(pre_o ? &A.w.hflag[m] : nullptr, pre_p ? &A.w.pflag[m] : nullptr,
+                         t2 ? &A.w.tflag[tidx(A, m, C - 2)] : nullptr, t3 ? &A.w.tflag[tidx(A, m, C - 3)] : nullptr,
+                         A.w);
     if (wave == 3) {
       const glb_t<F>* po = A.w.pre + m * 3 * T * T;
       v4_t<F> acc[7];  // blocks 0-3: (m, C), b -> (b & 1, b >> 1); 4-6: (m, m), (0,0) (1,0) (1,1)
@@ -769,28 +802,43 @@ __device__ void spine(const Args<F>& A, lds_t<F>* base, lds_i* s_fail, lds_i* s_
 
 // Ticket order: 0 = spine; then per column C the tiles O(C+3..C+K, C) in
 // pairs (the last one alone when their count is odd), with H(C+4) after the
-// first two pairs (its last terms use the tiles of those pairs).
+// first pair and P(C+5) after the second (their last terms use those pairs'
+// tiles).
 __host__ __device__ __forceinline__ unsigned off_pairs(int K) { return K >= 3 ? (unsigned)(K - 1) / 2u : 0u; }
-__host__ __device__ __forceinline__ unsigned tickets_per_column(int K) { return off_pairs(K) + (K >= 4 ? 1u : 0u); }
+__host__ __device__ __forceinline__ unsigned tickets_per_column(int K) {
+  return off_pairs(K) + (K >= 4 ? 1u : 0u) + (K >= 5 ? 1u : 0u);
+}
 
-// kind 1: tile (R, C); kind 3: tiles (R, C) and (R+1, C); kind 2: H(R).
+// kind 1: tile (R, C); kind 3: tiles (R, C) and (R+1, C); kind 2: H(R); kind 4: P(R).
 template <typename F>
 __device__ __forceinline__ void decode(const Args<F>& A, unsigned t, int& kind, int64_t& R, int64_t& C) {
   const unsigned per = tickets_per_column(A.K);
   const unsigned u = t - 1;
   C = u / per;
-  unsigned slot = u % per;
+  unsigned k = u % per;
   const unsigned np = off_pairs(A.K);
-  const unsigned hs = np < 2u ? np : 2u;
-  if (A.K >= 4) {
-    if (slot == hs) {
-      kind = 2;
-      R = C + 4;
-      return;
-    }
-    if (slot > hs) --slot;
+  unsigned pair = 0;
+  if (np >= 1) {
+    if (k == 0) goto off;
+    --k;
+    pair = 1;
   }
-  R = C + 3 + 2 * (int64_t)slot;
+  if (A.K >= 4) {
+    if (k == 0) { kind = 2; R = C + 4; return; }
+    --k;
+  }
+  if (np >= 2) {
+    if (k == 0) goto off;
+    --k;
+    pair = 2;
+  }
+  if (A.K >= 5) {
+    if (k == 0) { kind = 4; R = C + 5; return; }
+    --k;
+  }
+  pair += k;
+off:
+  R = C + 3 + 2 * (int64_t)pair;
   kind = (R + 1 <= C + A.K && R + 1 < A.NB) ? 3 : 1;
 }
 
@@ -819,7 +867,8 @@ __global__ void __launch_bounds__(NT, 2) factor2_kernel(Args<F> A) {
       if (R < A.NB) {
         if (kind == 1) task_off<F>(A, R, C, (lds_t<F>*)lds, (lds_i*)&s_ok);
         else if (kind == 3) task_off2<F>(A, R, C, (lds_t<F>*)lds, (lds_i*)&s_ok);
-        else task_pre(A, R, (lds_i*)&s_ok);
+        else if (kind == 2) task_pre(A, R, (lds_i*)&s_ok);
+        else task_p(A, R, (lds_i*)&s_ok);
       }
     }
     __syncthreads();
@@ -845,7 +894,7 @@ __global__ void factor2_finish(const glb_i* abort_flag, const unsigned long long
 static size_t factor2_workspace(int64_t n, int64_t K, size_t elem) {
   using namespace bandchol_f2;
   const int64_t NB = (n + T - 1) / T;
-  const size_t flags = sizeof(int) * (size_t)(NB * (K + 1) + NB);
+  const size_t flags = sizeof(int) * (size_t)(NB * (K + 1) + 2 * NB);
   return 256 + ((flags + 255) & ~(size_t)255) + elem * (size_t)NB * T * T * 4;
 }
 
@@ -870,11 +919,12 @@ static hipError_t factor2_launch(int64_t n, int64_t k, F* ab, int64_t ldab, int6
   A.w.zero = (const glb_t<F>*)(base + 64);
   A.w.tflag = (glb_i*)(base + 256);
   A.w.hflag = A.w.tflag + (size_t)NB * (K + 1);
-  const size_t flags = sizeof(int) * (size_t)(NB * (K + 1) + NB);
+  A.w.pflag = A.w.hflag + NB;
+  const size_t flags = sizeof(int) * (size_t)(NB * (K + 1) + 2 * NB);
   A.w.linvt = (glb_t<F>*)(base + 256 + ((flags + 255) & ~(size_t)255));
   A.w.pre = A.w.linvt + (size_t)NB * T * T;
   A.ntickets = 1 + tickets_per_column(K) * (unsigned)NB;
-  const int64_t nflags = (int64_t)NB * (K + 1) + NB;
+  const int64_t nflags = (int64_t)NB * (K + 1) + 2 * NB;
   factor2_init<<<(unsigned)((nflags + 255) / 256 > 1024 ? 1024 : (nflags + 255) / 256 + 1), 256, 0, st>>>(
       A.w.tflag, nflags, A.w.queue, A.w.abort_flag, A.w.first_fail, (unsigned long long*)(base + 64));
   int grid = grid_max;
