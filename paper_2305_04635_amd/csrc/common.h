@@ -342,9 +342,12 @@ __device__ __forceinline__ int sweep_ldlt(F (&row)[T], lds_t<F>* sq, lds_t<F>* s
   mid();
   dcur = readlane(row[H], H);
   sweep_half(row, H, dcur, d_mine, fail);
-  const F s_mine = prec_sqrt(d_mine);
+  // column c scaled by sqrt(d_c): the roots broadcast through LDS (lane c
+  // writes its own; within one wave LDS accesses complete in order), which
+  // keeps 2T lane reads off the vector ALU
+  if (lane < T) sd[lane] = prec_sqrt(d_mine);
 #pragma unroll
-  for (int c = 0; c < T; ++c) row[c] *= readlane(s_mine, c);
+  for (int c = 0; c < T; ++c) row[c] *= sd[c];
   return fail;
 }
 

@@ -432,7 +432,7 @@ __device__ __attribute__((noinline)) void task_p(const Args<F>& A_, int64_t m, l
 template <typename F>
 struct SpineLds {
   lds_t<F>* diag;        // staged diagonal tile D(C) (column-major, LP); scratch of the sweep
-  lds_t<F>* sd;          // T/2 pivots, scratch of the sweep
+  lds_t<F>* sd;          // T values, scratch of the sweep
   lds_t<F>* linvt;       // L(C,C)^{-T}, row-major, row pitch LP
   lds_t<F>* linvt_prev;  // L(C-1,C-1)^{-T}
   lds_t<F>* acco;        // tile (C+1, C) before its trsm
@@ -484,11 +484,13 @@ __device__ __forceinline__ void spine_sweep(lds_t<F>* diag, lds_t<F>* sd, lds_t<
     }
     return;
   }
+  // lane < T: row lane of L(C,C) into diag (column-major); lane >= T: row
+  // lane - T of L^{-T} into linvt (row-major); one write per column, each
+  // lane through its own base and stride (no branch per column)
+  lds_t<F>* const p0 = lane < T ? diag + lane : linvt + (lane - T) * LP;
+  const int step = lane < T ? LP : 1;
 #pragma unroll
-  for (int c = 0; c < T; ++c) {
-    if (lane < T) diag[c * LP + lane] = row[c];
-    else linvt[(lane - T) * LP + c] = row[c];
-  }
+  for (int c = 0; c < T; ++c) p0[c * step] = row[c];
 }
 
 // L(C,C) from LDS (column-major, pitch LP) to the band, lower triangle: lane
@@ -542,6 +544,23 @@ __device__ __forceinline__ bool wave_wait4(const glb_i* f0, const glb_i* f1, con
   return true;
 }
 
+// The helper flags step C of the spine waits for (null: not needed there).
+template <typename F>
+struct StepFlags {
+  const glb_i* f[4];
+};
+template <typename F>
+__device__ __forceinline__ StepFlags<F> step_flags(const Args<F>& A, int64_t C) {
+  const int K = A.K;
+  const int64_t m = C + 1;
+  StepFlags<F> r;
+  r.f[0] = K >= 4 && m >= 4 ? &A.w.hflag[m] : nullptr;                // H(m)
+  r.f[1] = K >= 5 && C >= 4 ? &A.w.pflag[m] : nullptr;                // P(m)
+  r.f[2] = K >= 3 && C >= 2 ? &A.w.tflag[tidx(A, m, C - 2)] : nullptr;  // L(m, C-2)
+  r.f[3] = K >= 4 && C >= 3 ? &A.w.tflag[tidx(A, m, C - 3)] : nullptr;  // L(m, C-3)
+  return r;
+}
+
 // Flags between waves 1-3 inside phase A, where wave 0 is sweeping and no
 // workgroup barrier can be used.  A wave's LDS accesses reach the LDS in
 // order, so a flag written after a wave's data is seen after that data.
@@ -573,7 +592,7 @@ __device__ __forceinline__ bool lds_wait(lds_i* f, int v) {
 //     their row half, wave 3 block (1, 0) of (m, m)).
 template <typename F>
 __device__ __forceinline__ void spine_prepare(const Args<F>& A, int64_t C, const SpineLds<F>& S, bool next,
-                                              lds_i* sync, lds_i* s_pub, lds_i* s_fail) {
+                                              lds_i* sync, lds_i* s_pub, lds_i* s_fail, int& early) {
   const int wave = wave_id();
   const int lane = lane_id();
   const int K = A.K;
@@ -586,9 +605,15 @@ __device__ __forceinline__ void spine_prepare(const Args<F>& A, int64_t C, const
     const bool t2 = K >= 3 && C >= 2;     // term s = C-2: L(m, C-2)
     const bool t3 = K >= 4 && C >= 3;     // term s = C-3 of (m, C-1): L(m, C-3)
     const int tag = (int)C + 1;
-    bool ok = wave_wait4(pre_o ? &A.w.hflag[m] : nullptr, pre_p ? &A.w.pflag[m] : nullptr,
-                         t2 ? &A.w.tflag[tidx(A, m, C - 2)] : nullptr, t3 ? &A.w.tflag[tidx(A, m, C - 3)] : nullptr,
-                         A.w);
+    // `early`: this lane's flag as read at the end of the previous step (1 if
+    // none is needed); all set means no poll now
+    bool ok = true;
+    if (__ballot(early == 0) != 0) {
+      const StepFlags<F> fl = step_flags(A, C);
+      ok = wave_wait4(fl.f[0], fl.f[1], fl.f[2], fl.f[3], A.w);
+    } else {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");  // keeps the operand loads below the flags
+    }
     if (wave == 3) {
       const glb_t<F>* po = A.w.pre + m * 3 * T * T;
       v4_t<F> acc[7];  // blocks 0-3: (m, C), b -> (b & 1, b >> 1); 4-6: (m, m), (0,0) (1,0) (1,1)
@@ -635,16 +660,21 @@ __device__ __forceinline__ void spine_prepare(const Args<F>& A, int64_t C, const
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj)
           pp[bj] = pre_p ? wblk_load(A.w.pre + C * 3 * T * T + 2 * T * T, h, bj) : ablk_load(A.a, m, C - 1, h, bj);
-        if (t2) {
-          term_load_x(A, m, C - 2, h, x3);
-          term_load_x(A, C - 1, C - 2, 0, y1[0]);
-          term_load_x(A, C - 1, C - 2, 1, y1[1]);
-        }
-        if (t3) {
-          term_load_x(A, m, C - 3, h, x4);
-          term_load_x(A, C - 1, C - 3, 0, y2[0]);
-          term_load_x(A, C - 1, C - 3, 1, y2[1]);
-        }
+        if (t2) term_load_x(A, m, C - 2, h, x3);
+        if (t3) term_load_x(A, m, C - 3, h, x4);
+        // L(C-1, C-2) and L(C-1, C-3), computed by the spine two steps ago,
+        // still sit in the buffers now called lcur and l2cur: read them before
+        // either wave overwrites those buffers
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+          for (int q = 0; q < T / 4; ++q) {
+            const int ix = (4 * q + (lane >> 4)) * LP + 16 * bj + (lane & 15);
+            y1[bj][q] = t2 ? S.lcur[ix] : F(0);
+            y2[bj][q] = t3 ? S.l2cur[ix] : F(0);
+          }
+        lds_signal(&sync[3 + h], tag);
+        if (!lds_wait(&sync[4 - h], tag)) ok = false;
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) {
           if (t3) pp[bj] = term_apply(x4, y2[bj], pp[bj]);
@@ -685,6 +715,12 @@ __device__ __forceinline__ void spine_prepare(const Args<F>& A, int64_t C, const
       if (K >= 1) raise_flag(&A.w.tflag[tidx(A, C, C - 1)]);
       if (K >= 2 && C >= 2) raise_flag(&A.w.tflag[tidx(A, C, C - 2)]);
     }
+  }
+  // the next step's flags, read now and used then (a load in flight meanwhile)
+  early = 1;
+  if (C + 2 < A.NB && lane < 4) {
+    const glb_i* f = step_flags(A, C + 1).f[lane];
+    if (f) early = __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -730,10 +766,11 @@ __device__ __attribute__((noinline)) void spine_waves123(const Args<F>& A_, cons
   SpineLds<F> S = S_;
   const BandT<F>& a = A.a;
   const int wave = wave_id();
+  int early = 0;
   for (int64_t C = 0; C < A.NB; ++C) {
     const bool next = C + 1 < A.NB;
     // phase A
-    spine_prepare(A, C, S, next, sync, s_pub, s_fail);
+    spine_prepare(A, C, S, next, sync, s_pub, s_fail, early);
     lds_barrier();
     if (*s_fail != -1) return;
     if (!next) {
@@ -784,7 +821,7 @@ __device__ void spine(const Args<F>& A, lds_t<F>* base, lds_i* s_fail, lds_i* s_
   if (threadIdx.x == 0) {
     *s_fail = -1;
     *s_pub = 0;
-    sync[0] = sync[1] = sync[2] = 0;
+    sync[0] = sync[1] = sync[2] = sync[3] = sync[4] = 0;
   }
   // stage tile (0,0)
   if (wave >= 1) {
@@ -844,8 +881,8 @@ off:
 
 template <typename F>
 __global__ void __launch_bounds__(NT, 2) factor2_kernel(Args<F> A) {
-  __shared__ F lds[9 * T * LP + T / 2];
-  __shared__ int s_ticket, s_ok, s_abort, s_pub, s_sync[3];
+  __shared__ F lds[9 * T * LP + T];
+  __shared__ int s_ticket, s_ok, s_abort, s_pub, s_sync[5];
   for (;;) {
     if (threadIdx.x == 0) {
       s_ticket = (int)atomicAdd(A.w.queue, 1u);
