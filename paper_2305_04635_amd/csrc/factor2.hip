@@ -512,9 +512,10 @@ __device__ __forceinline__ void store_lcc(const lds_t<F>* lcc, int64_t C, const 
   }
 }
 
-// Workgroup barrier for LDS data only: unlike __syncthreads it does not wait
-// for this wave's global stores, which only other workgroups read (after a
-// flag raised once they have drained).
+// Workgroup barrier for the LDS data of the spine: this wave's LDS accesses
+// complete (lgkmcnt(0)), then s_barrier; global stores, which only other
+// workgroups read (after a flag raised once they have drained), are not
+// waited for.
 __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
