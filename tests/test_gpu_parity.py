@@ -151,6 +151,26 @@ def test_both_schedules(schedule, n, k):
     assert info == 0 and np.array_equal(l_gpu, l0)
 
 
+@pytest.mark.parametrize("K", range(1, 11))
+def test_tile_schedule_each_K(K):
+    """The multi-workgroup schedule at every number of sub-diagonal tiles K = 1..10
+    (which of the spine's extra terms and of the helper tasks exist changes
+    with K up to 5), with k ragged in the last tile and n ragged, at a few tile
+    rows past K and at many; the integer factor must come out bit for bit."""
+    import paper_2305_04635_amd as bc
+    prev = bc.set_walk_limit(0)
+    try:
+        k = 32 * K - 5
+        for n in (32 * (K + 2) + 7, 32 * (3 * K + 6) - 3):
+            ab = synth.band_diagdom(n, k, 7 * n + K)
+            check_against_oracle(ab, k, nrhs=1, seed=K)
+            l0 = synth.int_factor(n, k, 11 + K, pow2_max=1)
+            l_gpu, info = gpu_factor(synth.band_ldlt(l0, k), k)
+            assert info == 0 and np.array_equal(l_gpu, l0), (n, k)
+    finally:
+        bc.set_walk_limit(prev)
+
+
 @pytest.mark.parametrize("n,k,nrhs", [(5000, 300, 20), (3000, 40, 9), (700, 699, 4), (4097, 250, 1)])
 def test_solve_many_rhs_and_wide_bands(n, k, nrhs):
     """Solves with more right-hand sides than one launch takes and bands wide
