@@ -49,6 +49,7 @@ struct Ws {
   unsigned* queue;
   glb_i* abort_flag;  // 1 = pivot failure, 2 = wait bound exceeded
   unsigned long long* first_fail;
+  glb_i* spine_cu;  // the spine's CU (cu_ident), -1 before it starts
   const glb_t<F>* zero;  // a zero: masked-off lanes load it, so that operand loads are unconditional
 };
 
@@ -64,6 +65,14 @@ __device__ __forceinline__ int aflag(const glb_i* p) {
   return __builtin_amdgcn_readfirstlane(__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
 }
 __device__ __forceinline__ void raise_flag(glb_i* p) { __hip_atomic_store(p, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+
+// The CU this wave runs on: HW_ID bits 8-15 (CU, shader array, engine) and the
+// XCC number.
+__device__ __forceinline__ int cu_ident() {
+  const int hw = __builtin_amdgcn_s_getreg(4 | (8 << 6) | (7 << 11));   // HW_ID[15:8]
+  const int xcc = __builtin_amdgcn_s_getreg(20 | (0 << 6) | (3 << 11));  // XCC_ID[3:0]
+  return hw | (xcc << 8);
+}
 
 // This wave waits for *f (bounded); every lane gets the same answer.
 template <typename F>
@@ -820,6 +829,7 @@ __device__ void spine(const Args<F>& A, lds_t<F>* base, lds_i* s_fail, lds_i* s_
   S.l2prev = S.l2cur + T * LP;
   S.sd = S.l2prev + T * LP;
   if (threadIdx.x == 0) {
+    __hip_atomic_store(A.w.spine_cu, cu_ident(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     *s_fail = -1;
     *s_pub = 0;
     sync[0] = sync[1] = sync[2] = sync[3] = sync[4] = 0;
@@ -886,7 +896,10 @@ __global__ void __launch_bounds__(NT, 2) factor2_kernel(Args<F> A) {
   __shared__ int s_ticket, s_ok, s_abort, s_pub, s_sync[5];
   for (;;) {
     if (threadIdx.x == 0) {
-      s_ticket = (int)atomicAdd(A.w.queue, 1u);
+      // a helper that shares the spine's CU takes no more tasks: the spine's
+      // waves then have the CU's matrix cores to themselves
+      const bool beside = __hip_atomic_load(A.w.spine_cu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == cu_ident();
+      s_ticket = beside ? -1 : (int)atomicAdd(A.w.queue, 1u);
       s_abort = aflag(A.w.abort_flag);
     }
     __syncthreads();
@@ -914,10 +927,10 @@ __global__ void __launch_bounds__(NT, 2) factor2_kernel(Args<F> A) {
 }
 
 __global__ void factor2_init(glb_i* flags, int64_t count, unsigned* queue, glb_i* abort_flag, unsigned long long* ff,
-                             unsigned long long* zero) {
+                             unsigned long long* zero, glb_i* spine_cu) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t x = g; x < count; x += (int64_t)gridDim.x * blockDim.x) flags[x] = 0;
-  if (g == 0) { *queue = 0; *abort_flag = 0; *ff = 0x7fffffffffffffffULL; *zero = 0; }
+  if (g == 0) { *queue = 0; *abort_flag = 0; *ff = 0x7fffffffffffffffULL; *zero = 0; *spine_cu = -1; }
 }
 
 __global__ void factor2_finish(const glb_i* abort_flag, const unsigned long long* ff, int64_t* d_info) {
@@ -954,6 +967,7 @@ static hipError_t factor2_launch(int64_t n, int64_t k, F* ab, int64_t ldab, int6
   A.w.queue = (unsigned*)base;
   A.w.abort_flag = (glb_i*)(base + 8);
   A.w.first_fail = (unsigned long long*)(base + 16);
+  A.w.spine_cu = (glb_i*)(base + 24);
   A.w.zero = (const glb_t<F>*)(base + 64);
   A.w.tflag = (glb_i*)(base + 256);
   A.w.hflag = A.w.tflag + (size_t)NB * (K + 1);
@@ -964,7 +978,7 @@ static hipError_t factor2_launch(int64_t n, int64_t k, F* ab, int64_t ldab, int6
   A.ntickets = 1 + tickets_per_column(K) * (unsigned)NB;
   const int64_t nflags = (int64_t)NB * (K + 1) + 2 * NB;
   factor2_init<<<(unsigned)((nflags + 255) / 256 > 1024 ? 1024 : (nflags + 255) / 256 + 1), 256, 0, st>>>(
-      A.w.tflag, nflags, A.w.queue, A.w.abort_flag, A.w.first_fail, (unsigned long long*)(base + 64));
+      A.w.tflag, nflags, A.w.queue, A.w.abort_flag, A.w.first_fail, (unsigned long long*)(base + 64), A.w.spine_cu);
   int grid = grid_max;
   if ((unsigned)grid > A.ntickets) grid = (int)A.ntickets;
   factor2_kernel<F><<<grid, NT, 0, st>>>(A);
