@@ -45,6 +45,13 @@ template <> struct Prec<float> {
 };
 template <typename F> using v4_t = typename Prec<F>::v4;
 
+// With v_mfma_f64_16x16x4f64 an accumulator block (bi, kb) holds, in register
+// r, exactly the operand fragment of k-step 4 kb + r of its row block (lane l:
+// column 16 kb + 4 r + l/16), so a product's result feeds the next product
+// without passing through LDS.  Not so for the FP32 instruction's layout.
+template <typename F>
+__host__ __device__ constexpr bool acc_is_operand() { return Prec<F>::ACC_STEP == 4; }
+
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 

@@ -664,6 +664,7 @@ __device__ __forceinline__ void spine_prepare(const Args<F>& A, int64_t C, const
       }
     } else {
       const int h = wave - 1;
+      v4_t<F> out[2];  // row half h of L(m, C-1), blocks (h, 0) and (h, 1)
       if (has_p) {
         v4_t<F> pp[2];
         F x3[T / 4], x4[T / 4], y1[2][T / 4], y2[2][T / 4];
@@ -689,13 +690,29 @@ __device__ __forceinline__ void spine_prepare(const Args<F>& A, int64_t C, const
         for (int bj = 0; bj < 2; ++bj) {
           if (t3) pp[bj] = term_apply(x4, y2[bj], pp[bj]);
           if (t2) pp[bj] = term_apply(x3, y1[bj], pp[bj]);
-          blk_to_lds(S.lcur, h, bj, pp[bj]);
+        }
+        if constexpr (acc_is_operand<F>()) {
+          // L(m, C-1) = P L(C-1,C-1)^{-T} straight from the accumulators
+          // (L^{-T} upper triangular: block (h, 0) takes columns 0-15 of P only)
+          out[0] = out[1] = v4_t<F>{0, 0, 0, 0};
+#pragma unroll
+          for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int kk = 16 * kb + 4 * r + (lane >> 4);
+              if (kb == 0) out[0] = mfma_xyt(pp[0][r], S.linvt_prev[kk * LP + (lane & 15)], out[0]);
+              out[1] = mfma_xyt(pp[kb][r], S.linvt_prev[kk * LP + 16 + (lane & 15)], out[1]);
+            }
+        } else {
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj) blk_to_lds(S.lcur, h, bj, pp[bj]);
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj) out[bj] = blk_trsm_lds<F>(S.lcur, S.linvt_prev, h, bj, LP);
         }
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) {
-          const v4_t<F> out = blk_trsm_lds<F>(S.lcur, S.linvt_prev, h, bj, LP);
-          blk_to_lds(S.l2cur, h, bj, out);
-          ablk_store(A.a, m, C - 1, h, bj, out);
+          blk_to_lds(S.l2cur, h, bj, out[bj]);
+          ablk_store(A.a, m, C - 1, h, bj, out[bj]);
         }
       }
       if (wave == 1 && copy0) ablk_store(A.a, C, C - 1, 0, 0, blk_from_lds<F>(S.lprev, 0, 0));
@@ -703,15 +720,35 @@ __device__ __forceinline__ void spine_prepare(const Args<F>& A, int64_t C, const
       if (!lds_wait(&sync[2], tag)) {
         ok = false;
       } else if (has_p) {
+        if constexpr (acc_is_operand<F>()) {
+          // X = this wave's rows of L(m, C-1), still in registers
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj) {
-          v4_t<F> v = blk_from_lds<F>(S.acco, h, bj);
-          v = blk_gemm_lds<F>(S.l2cur, S.lprev, h, bj, v);
-          blk_to_lds(S.acco, h, bj, v);
+          for (int bj = 0; bj < 2; ++bj) {
+            v4_t<F> v = blk_from_lds<F>(S.acco, h, bj);
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+              for (int r = 0; r < 4; ++r)
+                v = mfma_xyt(-out[kb][r], S.lprev[(16 * kb + 4 * r + (lane >> 4)) * LP + 16 * bj + (lane & 15)], v);
+            blk_to_lds(S.acco, h, bj, v);
+          }
+          v4_t<F> v = blk_from_lds<F>(S.accd, h, h);
+#pragma unroll
+          for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v = mfma_xyt(-out[kb][r], out[kb][r], v);
+          blk_to_lds(S.accd, h, h, v);
+        } else {
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj) {
+            v4_t<F> v = blk_from_lds<F>(S.acco, h, bj);
+            v = blk_gemm_lds<F>(S.l2cur, S.lprev, h, bj, v);
+            blk_to_lds(S.acco, h, bj, v);
+          }
+          v4_t<F> v = blk_from_lds<F>(S.accd, h, h);
+          v = blk_gemm_lds<F>(S.l2cur, S.l2cur, h, h, v);
+          blk_to_lds(S.accd, h, h, v);
         }
-        v4_t<F> v = blk_from_lds<F>(S.accd, h, h);
-        v = blk_gemm_lds<F>(S.l2cur, S.l2cur, h, h, v);
-        blk_to_lds(S.accd, h, h, v);
       }
     }
     if (!ok && lane == 0) *s_fail = -2;
