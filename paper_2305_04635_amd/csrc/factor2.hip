@@ -58,6 +58,7 @@ struct Args {
   BandT<F> a;
   int NB, K;
   unsigned ntickets;
+  int spare_spine_cu;  // a helper on the spine's CU stops (only with many workgroups)
   Ws<F> w;
 };
 
@@ -935,7 +936,8 @@ __global__ void __launch_bounds__(NT, 2) factor2_kernel(Args<F> A) {
     if (threadIdx.x == 0) {
       // a helper that shares the spine's CU takes no more tasks: the spine's
       // waves then have the CU's matrix cores to themselves
-      const bool beside = __hip_atomic_load(A.w.spine_cu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == cu_ident();
+      const bool beside = A.spare_spine_cu &&
+                          __hip_atomic_load(A.w.spine_cu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == cu_ident();
       s_ticket = beside ? -1 : (int)atomicAdd(A.w.queue, 1u);
       s_abort = aflag(A.w.abort_flag);
     }
@@ -1018,6 +1020,7 @@ static hipError_t factor2_launch(int64_t n, int64_t k, F* ab, int64_t ldab, int6
       A.w.tflag, nflags, A.w.queue, A.w.abort_flag, A.w.first_fail, (unsigned long long*)(base + 64), A.w.spine_cu);
   int grid = grid_max;
   if ((unsigned)grid > A.ntickets) grid = (int)A.ntickets;
+  A.spare_spine_cu = grid >= 64 ? 1 : 0;  // with few workgroups every helper counts
   factor2_kernel<F><<<grid, NT, 0, st>>>(A);
   factor2_finish<<<1, 1, 0, st>>>(A.w.abort_flag, A.w.first_fail, d_info);
   return hipGetLastError();

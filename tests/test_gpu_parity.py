@@ -171,6 +171,24 @@ def test_tile_schedule_each_K(K):
         bc.set_walk_limit(prev)
 
 
+@pytest.mark.parametrize("wg", [2, 3])
+def test_tile_schedule_few_workgroups(wg, monkeypatch):
+    """The multi-workgroup schedule with one or two helper workgroups: every
+    task only waits for earlier tickets or for spine steps, so it completes
+    (and correctly) whatever the number of workgroups."""
+    import paper_2305_04635_amd as bc
+    monkeypatch.setenv("BANDCHOL_MAX_WG", str(wg))
+    prev = bc.set_walk_limit(0)
+    try:
+        for K in (3, 4, 5, 6, 9):
+            n, k = 32 * (2 * K + 4) + 5, 32 * K - 3
+            l0 = synth.int_factor(n, k, 23 + K, pow2_max=1)
+            l_gpu, info = gpu_factor(synth.band_ldlt(l0, k), k)
+            assert info == 0 and np.array_equal(l_gpu, l0), (wg, n, k)
+    finally:
+        bc.set_walk_limit(prev)
+
+
 @pytest.mark.parametrize("n,k,nrhs", [(5000, 300, 20), (3000, 40, 9), (700, 699, 4), (4097, 250, 1)])
 def test_solve_many_rhs_and_wide_bands(n, k, nrhs):
     """Solves with more right-hand sides than one launch takes and bands wide
