@@ -5,7 +5,8 @@
 // the spine (whoever takes ticket 0), carries the dependency chain along the
 // diagonal and the first two sub-diagonals, one tile column per step C:
 //   phase A  wave 0: factor the staged diagonal tile (register sweep) ->
-//            L(C,C) and L(C,C)^{-T}, stored at once;
+//            L(C,C) and L(C,C)^{-T} in LDS (to global memory during phase C
+//            and the next sweep);
 //            waves 1-3: L(C+1, C-1) from its pre-accumulated sum, the terms
 //            s = C-3, C-2 and the previous step's L(C-1,C-1)^{-T}; then tile
 //            (C+1, C) and the next diagonal tile with the terms s = C-2, C-1;
@@ -447,9 +448,10 @@ struct SpineLds {
   lds_t<F>* linvt_prev;  // L(C-1,C-1)^{-T}
   lds_t<F>* acco;        // tile (C+1, C) before its trsm
   lds_t<F>* accd;        // tile (C+1, C+1) before its last term
-  lds_t<F>* lcur;        // L(C+1, C) from phase B; in phase A the staged tile (C+1, C-1)
+  lds_t<F>* lcur;        // L(C+1, C) from phase B; in phase A first L(C-1, C-2) (two steps old),
+                         // then (FP32) the staged tile (C+1, C-1)
   lds_t<F>* lprev;       // L(C, C-1)
-  lds_t<F>* l2cur;       // L(C+1, C-1)
+  lds_t<F>* l2cur;       // L(C+1, C-1); in phase A first L(C-1, C-3) (two steps old)
   lds_t<F>* l2prev;      // L(C, C-2)
 };
 
@@ -461,11 +463,9 @@ struct SpineLds {
 // have long completed, `flag_prev` is raised: the helpers' trsm takes
 // L(C-1,C-1)^{-T} from there.
 template <typename F>
-__device__ __forceinline__ void spine_sweep(lds_t<F>* diag, lds_t<F>* sd, lds_t<F>* linvt,
-                                                      const lds_t<F>* linvt_prev, glb_t<F>* lt_prev,
-                                                      glb_i* flag_prev, int64_t C, int64_t n,
-                                                      unsigned long long* first_fail, glb_i* abort_flag,
-                                                      lds_i* s_fail) {
+__device__ __forceinline__ void spine_sweep(lds_t<F>* diag, lds_t<F>* sd, lds_t<F>* linvt, const lds_t<F>* linvt_prev,
+                                            glb_t<F>* lt_prev, glb_i* flag_prev, int64_t C, int64_t n,
+                                            unsigned long long* first_fail, glb_i* abort_flag, lds_i* s_fail) {
   const int lane = lane_id();
   if (flag_prev) {
     const int r = lane & 31, h = lane >> 5;
@@ -596,8 +596,9 @@ __device__ __forceinline__ bool lds_wait(lds_i* f, int v) {
 //     that store); at the end each wave drains its stores and counts in, and
 //     the third raises the flags of L(C, C-1) and L(C, C-2);
 //   * tile (m, C-1): the helpers' sum over s <= C-4, here the terms s = C-3
-//     and C-2, then L(m, C-1) = tile L(C-1,C-1)^{-T} (the previous sweep's
-//     inverse, still in LDS); row half h on wave 1+h;
+//     and C-2 (operands L(C-1, C-3) and L(C-1, C-2) still in LDS), then
+//     L(m, C-1) = tile L(C-1,C-1)^{-T} (the previous sweep's inverse, also
+//     still in LDS); row half h on wave 1+h;
 //   * tiles (m, C) and (m, m): the helpers' sums over s <= C-3; here s = C-2
 //     (wave 3, all blocks), then s = C-1 with the new L(m, C-1) (waves 1 and 2
 //     their row half, wave 3 block (1, 0) of (m, m)).
