@@ -26,7 +26,8 @@ def gpu_factor_f32(a, k):
     return d.cpu().numpy().reshape(a.shape, order="F"), int(info.item())
 
 
-@pytest.mark.parametrize("n,k", [(3000, 50), (2000, 100), (1000, 250), (500, 499), (33, 32), (1, 0)])
+@pytest.mark.parametrize("n,k", [(3000, 50), (2000, 100), (1000, 155), (1337, 190), (1000, 250), (500, 499), (33, 32),
+                                 (1, 0)])
 def test_factor_f32_integer_exact(n, k):
     """Unit pivots only: the trsm multiplies by L(C,C)^{-T}, whose entries are
     then integers (below 2^15 for these seeds) and exact in FP32.  With pivots
