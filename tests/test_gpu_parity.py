@@ -171,6 +171,25 @@ def test_tile_schedule_each_K(K):
         bc.set_walk_limit(prev)
 
 
+@pytest.mark.parametrize("k", [50, 1000, 2000])
+def test_full_size_sampled(k):
+    """The benchmark's size and input recipe (n = 1e5, interior-point-like SPD
+    band) in its launch configuration (default schedule and workgroup count):
+    backward error of L on sampled row windows (the first, a middle and the
+    last 64 rows, each across tile boundaries) and the solve's residual over
+    the whole vector."""
+    n = 100000
+    ab, _ = synth.band_ipm(n, k, 1000 + k)
+    l_gpu, info = gpu_factor(ab, k)
+    assert info == 0
+    rows = [(0, 64), (n // 2 - 32, n // 2 + 32), (n - 64, n)]
+    eta = oracle.llt_residual(l_gpu, ab, k, rows=rows)
+    assert eta <= ETA_TOL, eta
+    b = synth.rhs(n, 1, k)
+    x = gpu_solve(l_gpu, k, b)
+    assert oracle.solve_residual(ab, k, x, b) <= ETA_TOL
+
+
 @pytest.mark.parametrize("wg", [2, 3])
 def test_tile_schedule_few_workgroups(wg, monkeypatch):
     """The multi-workgroup schedule with one or two helper workgroups: every
