@@ -99,6 +99,25 @@ def test_nonspd_info_matches_oracle(m, dval):
     assert info == m + 1 == oracle.factor(a, k)[1]
 
 
+@pytest.mark.parametrize("k", [180, 300])
+@pytest.mark.parametrize("m", [0, 33, 700, 2047])
+def test_nonspd_info_with_helpers(k, m):
+    """A failing pivot while helper workgroups are at work (K = 6 and 10): the
+    first failing column is reported as the oracle reports it, and every
+    waiting workgroup leaves through the abort flag (the call returns within the
+    test's time limit, far below the waits' own bound)."""
+    import time
+    n = 2048
+    l0 = synth.int_factor(n, k, 77 + k)
+    dvec = np.ones(n)
+    dvec[m] = -1.0
+    a = synth.band_ldlt(l0, k, dvec)
+    t0 = time.time()
+    _, info = gpu_factor(a, k)
+    assert time.time() - t0 < 2.0
+    assert info == m + 1 == oracle.factor(a, k)[1]
+
+
 def test_nan_info_matches_oracle():
     n, k = 400, 45
     base = synth.band_diagdom(n, k, 21)
