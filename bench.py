@@ -54,8 +54,9 @@ def solve_flops(n, k, nrhs):
     return 4 * n * k * nrhs
 
 
-# sources of the dominant kernel (the multi-workgroup spine/helper factor)
-KERNEL_SOURCES = ("factor2.hip", "common.h")
+# sources of the dominant kernel (the multi-workgroup spine/helper factor) and of
+# the host runtime that chooses its launch (workgroups per matrix)
+KERNEL_SOURCES = ("factor2.hip", "common.h", "bandchol.hip")
 
 
 def source_hash():
@@ -192,7 +193,8 @@ def main():
         f_ms = float(np.median([evs[s][i][0].elapsed_time(evs[s][i][1]) for s in range(args.steps)]))
         s_ms = float(np.median([evs[s][i][1].elapsed_time(evs[s][i][2]) for s in range(args.steps)]))
         ff = factor_flops(n, m["k"])
-        per_k.append({"k": m["k"], "factor_ms": round(f_ms, 4), "solve_ms": round(s_ms, 4),
+        per_k.append({"k": m["k"], "workgroups": bc.schedule(n, m["k"]), "factor_ms": round(f_ms, 4),
+                      "solve_ms": round(s_ms, 4),
                       "factor_gflops": round(ff / (f_ms * 1e-3) / 1e9, 2),
                       "factor_frac_fp64_peak": round(ff / (f_ms * 1e-3) / (PEAK_FP64_TFLOPS * 1e12), 5),
                       "factor_frac_hbm": round(16.0 * n * (m["k"] + 1) / (f_ms * 1e-3) / (PEAK_HBM_GBS * 1e9), 5)})

@@ -106,6 +106,62 @@ int64_t bandchol_tile(void);
 int64_t bandchol_set_walk_limit(int64_t kmax);
 
 /*
+ * Schedule per (n, k) bucket.  The paper picks the dimension of its block
+ * grid per problem with a heuristic (block size near 50, no more blocks than
+ * cores) and lets users who know their bandwidths and hardware tune it
+ * (Section 3, end of the method's overview).  Here the tile is fixed by the
+ * matrix instruction and the choice is the number of workgroups that factor
+ * one matrix:
+ * 1 = the single-workgroup walk, w >= 2 = the tile schedule with w
+ * workgroups (one carries the diagonal chain, the rest take tile tasks).
+ * Buckets are (floor(log2 n), K) with K = ceil(min(k, n-1) / bandchol_tile()).
+ * The factor (FP64, FP32, and the wide systems of batch plans when the plan is
+ * created) takes, in this order: the walk for K up to the walk limit
+ * (bandchol_set_walk_limit; by default K = 0 only), the table entry of the
+ * bucket, else the rule w = clamp(8 K rounded up to a multiple of 32, 64,
+ * 2 x CUs).  The FP32 factor has no walk and takes the rule where the choice
+ * is 1.  The table is process-wide and guarded by a mutex; it starts empty.
+ *
+ * bandchol_schedule: the workgroup count the factor of (n, k) would use now,
+ * 0 for n = 0; -1 / -2 for a bad n / k.  No GPU work.
+ *
+ * bandchol_tune_set: record w for the bucket of (n, k), replacing an entry;
+ * w = 0 removes the bucket's entry.  Returns -1 / -2 for a bad n / k, -3 when
+ * w < 0, w > 2 x CUs, w = 1 with K > 15 (the walk's limit) or w > 1 with
+ * K = 0.  No GPU work.
+ *
+ * bandchol_tune_entries: copies up to `cap` entries (arrays of `cap`
+ * elements: the n and k each was recorded for, its w, and its measured
+ * median factor time in ms, 0 when set by the caller) and returns the number
+ * of entries; cap = 0 only counts (NULL arrays allowed).  -1 when cap < 0,
+ * -2 .. -5 for a NULL array with cap > 0.
+ *
+ * bandchol_tune_clear: empties the table.
+ *
+ * bandchol_tune_factor: measures the factor of an (n, k) band on the current
+ * device, on the stream set for the calling thread, and records the fastest
+ * schedule for its bucket.  The test matrix is generated on the device
+ * (off-diagonal entries uniform in [-1, 1) from a hash of their position,
+ * diagonal 2k + 2: diagonally dominant, so SPD).  Candidates: the walk when
+ * K <= 15, and (for K >= 1) 32, 64, 96, 128, 192, 256, 320, 384, 448, 512 ...
+ * up to 2 x CUs workgroups plus the rule's count.  Each candidate runs once
+ * untimed (dropped when it takes more than twice the best median so far),
+ * then `reps` timed runs (1 <= reps <= 1000; events around the factor on the
+ * stream); the lowest median wins (ties: the earlier candidate).  Writes the
+ * winner and its median (ms) to *wgs_out / *ms_out when not NULL.  Allocates
+ * the test band (8 (k+1) n bytes) with hipMalloc and frees it before
+ * returning: not for use under stream capture.  Synchronous.  Returns -1 / -2
+ * / -3 for a bad n / k / reps, BANDCHOL_EHIP on a HIP error or if a
+ * factor fails (the table is then unchanged).  The BANDCHOL_MAX_WG
+ * environment cap, when set, applies to the candidates too.
+ */
+int64_t bandchol_schedule(int64_t n, int64_t k);
+int64_t bandchol_tune_set(int64_t n, int64_t k, int64_t wgs);
+int64_t bandchol_tune_entries(int64_t cap, int64_t* n, int64_t* k, int64_t* wgs, double* ms);
+void bandchol_tune_clear(void);
+int64_t bandchol_tune_factor(int64_t n, int64_t k, int64_t reps, int64_t* wgs_out, double* ms_out);
+
+/*
  * FP32 factor: the same factorization in single precision (the trailing
  * products on v_mfma_f32_16x16x4f32, FP32 accumulation), in place on a float
  * band in the same layout.  Arguments and info as bandchol_factor_async

@@ -40,6 +40,11 @@ SIGNATURES = {
     "bandchol_batch_backward": (_I64, [_VP, _I64, _VP]),
     "bandchol_factor_f32": (_I64, [_I64, _I64, _VP, _I64, _VP, _VP]),
     "bandchol_mixed_solve": (_I64, [_I64, _I64, _I64, _VP, _I64, _VP, _I64, _VP, _I64, _VP, _VP]),
+    "bandchol_schedule": (_I64, [_I64, _I64]),
+    "bandchol_tune_set": (_I64, [_I64, _I64, _I64]),
+    "bandchol_tune_entries": (_I64, [_I64, _VP, _VP, _VP, _VP]),
+    "bandchol_tune_clear": (None, []),
+    "bandchol_tune_factor": (_I64, [_I64, _I64, _I64, _VP, _VP]),
 }
 
 EHIP = -1000
@@ -90,6 +95,64 @@ def tile():
 def set_walk_limit(kmax):
     """Largest sub-diagonal tile count factored by the single-workgroup walk; returns the previous value."""
     return int(load().bandchol_set_walk_limit(int(kmax)))
+
+
+def schedule(n, k):
+    """Workgroups the factor of an (n, k) band uses now (1 = the walk)."""
+    rc = int(load().bandchol_schedule(int(n), int(k)))
+    if rc < 0:
+        _raise(rc, "bandchol_schedule")
+    return rc
+
+
+def tune_set(n, k, wgs):
+    """Record the workgroup count for the (n, k) bucket (0 removes the entry)."""
+    rc = int(load().bandchol_tune_set(int(n), int(k), int(wgs)))
+    if rc != 0:
+        _raise(rc, "bandchol_tune_set")
+
+
+def tune_entries():
+    """The schedule table: a list of dicts with keys n, k, wgs, ms."""
+    lib = load()
+    count = int(lib.bandchol_tune_entries(0, None, None, None, None))
+    if count == 0:
+        return []
+    n, k, w = (ctypes.c_int64 * count)(), (ctypes.c_int64 * count)(), (ctypes.c_int64 * count)()
+    ms = (ctypes.c_double * count)()
+    got = int(lib.bandchol_tune_entries(count, n, k, w, ms))
+    return [{"n": n[i], "k": k[i], "wgs": w[i], "ms": ms[i]} for i in range(min(got, count))]
+
+
+def tune_clear():
+    load().bandchol_tune_clear()
+
+
+def tune_factor(n, k, reps=3):
+    """Time the factor's schedules for an (n, k) band on the current device and
+    stream, record the fastest for its bucket; returns (wgs, median ms)."""
+    lib = load()
+    lib.bandchol_set_stream(_stream())
+    w, ms = ctypes.c_int64(0), ctypes.c_double(0.0)
+    rc = int(lib.bandchol_tune_factor(int(n), int(k), int(reps), ctypes.byref(w), ctypes.byref(ms)))
+    if rc != 0:
+        _raise(rc, "bandchol_tune_factor")
+    return int(w.value), float(ms.value)
+
+
+def save_tuning(path):
+    """Write the schedule table as JSON."""
+    import json
+    with open(path, "w") as f:
+        json.dump(tune_entries(), f, indent=1)
+
+
+def load_tuning(path):
+    """Add the entries of a JSON schedule table written by save_tuning."""
+    import json
+    with open(path) as f:
+        for e in json.load(f):
+            tune_set(e["n"], e["k"], e["wgs"])
 
 
 def factor(ab, n, k, ldab=None):

@@ -175,14 +175,68 @@ int walk_kmax() {
 
 constexpr int64_t MIXED_ITMAX = 30;   // refinement corrections before the FP64 fallback
 
-int spine_grid() {
-  int grid = num_cus() * 2;
+// ------------------------------------------------------- schedule per bucket
+// The factor's schedule is a workgroup count: 1 = the single-workgroup walk,
+// more = the spine schedule with that many workgroups.  The count is looked up
+// per (floor(log2 n), K) bucket in a table filled by measurement
+// (bandchol_tune_factor) or by the caller (bandchol_tune_set); buckets without
+// an entry take the rule below.
+
+// Workgroups of the spine schedule that are resident at once (two per CU).
+int resident_wgs() { return num_cus() * 2; }
+
+int n_bucket(int64_t n) {
+  int b = 0;
+  while (b < 62 && (n >> (b + 1)) > 0) ++b;
+  return b;
+}
+
+// The rule for the spine: the helpers' work per tile column grows with K (the
+// tiles of a column, K + 1, each updated by up to K earlier columns), and
+// helpers beyond what the columns in flight can feed only contend for the
+// spine's memory and matrix cores.  Eight workgroups per tile diagonal, between
+// 64 and all resident ones.
+int spine_rule(int K) {
+  int g = ((8 * K + 31) / 32) * 32;
+  const int most = resident_wgs();
+  if (g < 64) g = 64;
+  if (g > most) g = most;
+  return g;
+}
+
+struct TuneEntry {
+  int nb = 0, K = 0, wgs = 0;
+  int64_t n = 0, k = 0;   // the system it was measured or set for
+  double ms = 0.0;        // measured factor time (0 when set by the caller)
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;
+
+// Workgroups for the factor of a system with these sizes (before the cap):
+// the walk up to the walk limit (by default diagonal matrices only), then the
+// table, then the rule.
+int schedule_wgs(int64_t n, int K) {
+  if (K <= walk_kmax()) return 1;
+  const int nb = n_bucket(n);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const TuneEntry& t : g_tune)
+      if (t.nb == nb && t.K == K) return t.wgs;
+  }
+  return spine_rule(K);
+}
+
+// Spine workgroup count after the BANDCHOL_MAX_WG cap (testing aid).
+int spine_grid(int want) {
+  int grid = want < 2 ? 2 : want;
   if (const char* cap = getenv("BANDCHOL_MAX_WG")) {
     const long v = strtol(cap, nullptr, 10);
     if (v > 0 && v < grid) grid = (int)v;
   }
   return grid;
 }
+
+int64_t factor_with(int64_t n, int64_t k, double* ab, int64_t ldab, int64_t* d_info, int wgs, hipStream_t st);
 
 int64_t factor_async_impl(int64_t n, int64_t k, double* ab, int64_t ldab, int64_t* d_info, hipStream_t st) {
   if (n < 0) return -1;
@@ -200,9 +254,15 @@ int64_t factor_async_impl(int64_t n, int64_t k, double* ab, int64_t ldab, int64_
     if (e != hipSuccess) { set_err("factor", e); return BANDCHOL_EHIP; }
     return 0;
   }
+  const int K = tile_diagonals(n, k);
+  return factor_with(n, k, ab, ldab, d_info, schedule_wgs(n, K), st);
+}
+
+// The factor with a given schedule (1 = walk, else spine workgroups).
+int64_t factor_with(int64_t n, int64_t k, double* ab, int64_t ldab, int64_t* d_info, int wgs, hipStream_t st) {
   hipError_t e;
   const int K = tile_diagonals(n, k);
-  if (K <= walk_kmax()) {
+  if (wgs == 1 && K <= WALK_KMAX) {
     const int64_t kk = k < n - 1 ? k : n - 1;
     e = bandchol_walk_single_launch(WalkSys{ab, n, kk, ldab, nullptr, nullptr, 0}, K, d_info, st);
     if (e != hipSuccess) { set_err("factor launch", e); return BANDCHOL_EHIP; }
@@ -210,7 +270,7 @@ int64_t factor_async_impl(int64_t n, int64_t k, double* ab, int64_t ldab, int64_
   }
   void* w2 = workspace(bandchol_factor2_workspace(n, K), &e);
   if (!w2) { set_err("workspace", e); return BANDCHOL_EHIP; }
-  e = bandchol_factor2_launch(n, k, ab, ldab, d_info, w2, spine_grid(), st);
+  e = bandchol_factor2_launch(n, k, ab, ldab, d_info, w2, spine_grid(wgs), st);
   if (e != hipSuccess) { set_err("factor launch", e); return BANDCHOL_EHIP; }
   return 0;
 }
@@ -278,7 +338,9 @@ int64_t factor_f32_impl(int64_t n, int64_t k, float* ab, int64_t ldab, int64_t* 
   }
   void* ws = workspace(bandchol_factor2_workspace_f32(n, tile_diagonals(n, k)), &e);
   if (!ws) { set_err("workspace", e); return BANDCHOL_EHIP; }
-  e = bandchol_factor2_launch_f32(n, k, ab, ldab, d_info, ws, spine_grid(), st);
+  const int K = tile_diagonals(n, k);
+  const int wgs = schedule_wgs(n, K);   // no FP32 walk: a walk choice takes the rule
+  e = bandchol_factor2_launch_f32(n, k, ab, ldab, d_info, ws, spine_grid(wgs == 1 ? spine_rule(K) : wgs), st);
   if (e != hipSuccess) { set_err("factor f32 launch", e); return BANDCHOL_EHIP; }
   return 0;
 }
@@ -423,6 +485,7 @@ struct bandchol_batch {
   // systems with K > WALK_KMAX: multi-workgroup factor and solve, one after another
   std::vector<WalkSys> wide;
   std::vector<int64_t> wide_id;
+  std::vector<int> wide_wgs;      // spine workgroups of wide[j] (schedule table or rule, at plan creation)
   // device memory
   void* mem = nullptr;            // descriptors, order, counters, info staging, wide workspace, inverses
   WalkSys* d_sys = nullptr;
@@ -446,6 +509,55 @@ namespace {
 __global__ void scatter_info_kernel(const int64_t* src, const int64_t* idx, int count, int64_t* dst) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j < count) dst[idx[j]] = src[j];
+}
+
+// Test matrix of the schedule measurement: band (n, kk) in ldab = kk + 1 with
+// off-diagonal entries uniform in [-1, 1) from the splitmix64 hash of their
+// position and diagonal 2 kk + 2, which exceeds every row's off-diagonal sum:
+// symmetric and strictly diagonally dominant, hence positive definite.
+__global__ void tune_fill_kernel(double* ab, int64_t n, int64_t kk) {
+  const int64_t w = kk + 1, total = n * w;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = t / w, i = t - j * w;
+    double v = 0.0;
+    if (i == 0) {
+      v = 2.0 * (double)kk + 2.0;
+    } else if (j + i < n) {
+      uint64_t z = (uint64_t)t + 0x9e3779b97f4a7c15ull;
+      z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+      z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+      z ^= z >> 31;
+      v = (double)(z >> 11) * 0x1.0p-52 - 1.0;
+    }
+    ab[t] = v;
+  }
+}
+
+// Schedules the measurement tries: the walk where it applies, then spine
+// workgroup counts up to the resident limit, and the rule's own count.
+std::vector<int> tune_candidates(int K) {
+  std::vector<int> c;
+  if (K <= WALK_KMAX) c.push_back(1);
+  if (K == 0) return c;   // a diagonal matrix has no tile tasks for helpers
+  const int most = resident_wgs();
+  for (int g : {32, 64, 96, 128, 192, 256, 320, 384, 448, 512, 640, 768, 1024})
+    if (g <= most) c.push_back(g);
+  const int r = spine_rule(K);
+  if (std::find(c.begin(), c.end(), r) == c.end()) c.push_back(r);
+  return c;
+}
+
+void tune_record(int64_t n, int64_t kk, int K, int wgs, double ms) {
+  const int nb = n_bucket(n);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (TuneEntry& t : g_tune)
+    if (t.nb == nb && t.K == K) {
+      t.wgs = wgs, t.n = n, t.k = kk, t.ms = ms;
+      return;
+    }
+  TuneEntry t;
+  t.nb = nb, t.K = K, t.wgs = wgs, t.n = n, t.k = kk, t.ms = ms;
+  g_tune.push_back(t);
 }
 
 }  // namespace
@@ -571,6 +683,7 @@ int64_t bandchol_batch_create(int64_t batch, const int64_t* n, const int64_t* k,
     } else {
       p->wide.push_back(w);
       p->wide_id.push_back(i);
+      p->wide_wgs.push_back(schedule_wgs(n[i], K));
       wide_ws = std::max(wide_ws, std::max(bandchol_factor2_workspace(n[i], K), bandchol_solve_workspace(n[i], kk)));
     }
   }
@@ -633,7 +746,8 @@ int64_t bandchol_batch_factor(bandchol_batch_t p, int64_t* d_info, void* stream)
   }
   for (size_t j = 0; j < p->wide.size() && e == hipSuccess; ++j) {
     const WalkSys& w = p->wide[j];
-    e = bandchol_factor2_launch(w.n, w.k, w.ab, w.ldab, d_info + p->wide_id[j], p->d_wide_ws, spine_grid(), st);
+    e = bandchol_factor2_launch(w.n, w.k, w.ab, w.ldab, d_info + p->wide_id[j], p->d_wide_ws,
+                                spine_grid(p->wide_wgs[j]), st);
   }
   if (e != hipSuccess) { set_err("batch factor", e); return BANDCHOL_EHIP; }
   return 0;
@@ -750,6 +864,132 @@ int64_t bandchol_set_walk_limit(int64_t kmax) {
   if (kmax < 0) return prev;
   g_walk_kmax = (int)(kmax > WALK_KMAX ? WALK_KMAX : kmax);
   return prev;
+}
+
+int64_t bandchol_schedule(int64_t n, int64_t k) {
+  g_err[0] = 0;
+  if (n < 0 || n > ((int64_t)1 << 31) - T) return -1;
+  if (k < 0) return -2;
+  if (n == 0) return 0;
+  const int wgs = schedule_wgs(n, tile_diagonals(n, k));
+  return wgs == 1 ? 1 : spine_grid(wgs);
+}
+
+int64_t bandchol_tune_set(int64_t n, int64_t k, int64_t wgs) {
+  g_err[0] = 0;
+  if (n < 1 || n > ((int64_t)1 << 31) - T) return -1;
+  if (k < 0) return -2;
+  const int K = tile_diagonals(n, k);
+  if (wgs < 0 || (wgs == 1 && K > WALK_KMAX) || (wgs > 1 && K == 0) || wgs > resident_wgs()) return -3;
+  if (wgs == 0) {
+    const int nb = n_bucket(n);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.erase(std::remove_if(g_tune.begin(), g_tune.end(),
+                                [&](const TuneEntry& t) { return t.nb == nb && t.K == K; }),
+                 g_tune.end());
+    return 0;
+  }
+  tune_record(n, k < n - 1 ? k : n - 1, K, (int)wgs, 0.0);
+  return 0;
+}
+
+int64_t bandchol_tune_entries(int64_t cap, int64_t* n, int64_t* k, int64_t* wgs, double* ms) {
+  g_err[0] = 0;
+  if (cap < 0) return -1;
+  if (cap > 0 && n == nullptr) return -2;
+  if (cap > 0 && k == nullptr) return -3;
+  if (cap > 0 && wgs == nullptr) return -4;
+  if (cap > 0 && ms == nullptr) return -5;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  const int64_t count = (int64_t)g_tune.size();
+  for (int64_t i = 0; i < count && i < cap; ++i) {
+    n[i] = g_tune[i].n;
+    k[i] = g_tune[i].k;
+    wgs[i] = g_tune[i].wgs;
+    ms[i] = g_tune[i].ms;
+  }
+  return count;
+}
+
+void bandchol_tune_clear(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
+}
+
+int64_t bandchol_tune_factor(int64_t n, int64_t k, int64_t reps, int64_t* wgs_out, double* ms_out) {
+  g_err[0] = 0;
+  if (n < 1 || n > ((int64_t)1 << 31) - T) return -1;
+  if (k < 0) return -2;
+  if (reps < 1 || reps > 1000) return -3;
+  const int64_t kk = k < n - 1 ? k : n - 1;
+  const int K = tile_diagonals(n, k);
+  const std::vector<int> cand = tune_candidates(K);
+  hipStream_t st = g_stream;
+  double* ab = nullptr;
+  int64_t* d_info = nullptr;
+  int64_t* h_info = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int64_t rc = 0;
+  int best = 0;
+  double best_ms = 0.0;
+  hipError_t e = hipMalloc(&ab, sizeof(double) * (size_t)(kk + 1) * (size_t)n);
+  if (e == hipSuccess) e = hipMalloc(&d_info, 256);
+  if (e == hipSuccess) e = hipHostMalloc(&h_info, 64, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  const int64_t total = (kk + 1) * n;
+  const int fill_grid = (int)std::min<int64_t>((total + 255) / 256, 8192);
+  std::vector<float> t;
+  for (size_t c = 0; c < cand.size() && e == hipSuccess && rc == 0; ++c) {
+    t.clear();
+    for (int64_t r = 0; r <= reps && e == hipSuccess && rc == 0; ++r) {
+      tune_fill_kernel<<<fill_grid, 256, 0, st>>>(ab, n, kk);
+      e = hipGetLastError();
+      if (e == hipSuccess) e = hipEventRecord(e0, st);
+      if (e != hipSuccess) break;
+      rc = factor_with(n, kk, ab, kk + 1, d_info, cand[c], st);
+      if (rc != 0) break;
+      e = hipEventRecord(e1, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(h_info, d_info, sizeof(int64_t), hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) break;
+      if (*h_info != 0) {
+        snprintf(g_err, sizeof g_err, "tune: factor of the test matrix returned info %lld", (long long)*h_info);
+        rc = BANDCHOL_EHIP;
+        break;
+      }
+      if (r == 0) {
+        if (best > 0 && ms > 2.0 * best_ms) break;   // far behind the best: no timed runs
+        continue;
+      }
+      t.push_back(ms);
+    }
+    if ((int64_t)t.size() == reps) {
+      std::sort(t.begin(), t.end());
+      const double med = t[t.size() / 2];
+      if (best == 0 || med < best_ms) best = cand[c], best_ms = med;
+    }
+  }
+  if (e != hipSuccess && rc == 0) {
+    set_err("tune", e);
+    rc = BANDCHOL_EHIP;
+  }
+  if (rc == 0 && best == 0) {
+    snprintf(g_err, sizeof g_err, "tune: no schedule measured");
+    rc = BANDCHOL_EHIP;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (h_info) (void)hipHostFree(h_info);
+  if (d_info) (void)hipFree(d_info);
+  if (ab) (void)hipFree(ab);
+  if (rc != 0) return rc;
+  tune_record(n, kk, K, best, best_ms);
+  if (wgs_out) *wgs_out = best;
+  if (ms_out) *ms_out = best_ms;
+  return 0;
 }
 
 }  // extern "C"

@@ -106,3 +106,77 @@ def test_f32_and_mixed_bad_arguments_rejected_on_host():
     it, fb = ctypes.c_int64(7), ctypes.c_int64(7)
     assert m(0, 2, 1, None, 3, None, 1, None, 1, ctypes.byref(it), ctypes.byref(fb)) == 0
     assert it.value == 0 and fb.value == 0
+
+
+def test_schedule_rule_and_table_on_host(tmp_path, monkeypatch):
+    """The schedule per (n, k) bucket: the rule where the table has no entry,
+    table entries per (floor(log2 n), K) bucket, the walk limit first, the
+    argument checks, and a JSON round trip (host logic only)."""
+    monkeypatch.delenv("BANDCHOL_MAX_WG", raising=False)
+    lib = bc.load()
+    bc.tune_clear()
+    prev = bc.set_walk_limit(0)
+    try:
+        # rule: 8 workgroups per tile diagonal, rounded up to 32, within [64, 2 x 256 CUs]
+        assert bc.schedule(100000, 0) == 1            # diagonal: the walk
+        assert bc.schedule(100000, 50) == 64          # K = 2
+        assert bc.schedule(100000, 500) == 128        # K = 16
+        assert bc.schedule(100000, 1000) == 256       # K = 32
+        assert bc.schedule(100000, 1025) == 288       # K = 33: 264 -> 288
+        assert bc.schedule(100000, 1500) == 384       # K = 47: 376 -> 384
+        assert bc.schedule(100000, 2000) == 512       # K = 63
+        assert bc.schedule(100000, 99999) == 512      # clamped
+        assert bc.schedule(40, 1000) == 64            # k clipped to n - 1: K = 2
+        assert lib.bandchol_schedule(0, 5) == 0
+        assert lib.bandchol_schedule(-1, 5) == -1
+        assert lib.bandchol_schedule(5, -1) == -2
+        # the walk limit comes first
+        bc.set_walk_limit(3)
+        assert bc.schedule(1000, 96) == 1 and bc.schedule(1000, 97) == 64
+        bc.set_walk_limit(0)
+        # one entry per (floor(log2 n), K) bucket
+        bc.tune_set(100000, 1000, 384)
+        assert bc.schedule(100000, 1000) == 384
+        assert bc.schedule(70000, 993) == 384         # same bucket (16, 32)
+        assert bc.schedule(140000, 1000) == 256       # bucket 17: the rule
+        assert bc.schedule(100000, 1025) == 288       # K = 33: the rule
+        bc.tune_set(90000, 999, 320)                  # replaces the entry of bucket (16, 32)
+        assert bc.tune_entries() == [{"n": 90000, "k": 999, "wgs": 320, "ms": 0.0}]
+        bc.tune_set(1000, 480, 1)                     # K = 15: the walk is allowed
+        assert bc.schedule(1000, 470) == 1
+        bc.tune_set(200, 300, 2)                      # k clipped: recorded as 199
+        assert {"n": 200, "k": 199, "wgs": 2, "ms": 0.0} in bc.tune_entries()
+        # the environment cap applies to the tile schedule only
+        monkeypatch.setenv("BANDCHOL_MAX_WG", "100")
+        assert bc.schedule(90000, 999) == 100 and bc.schedule(1000, 470) == 1
+        monkeypatch.delenv("BANDCHOL_MAX_WG")
+        # JSON round trip
+        path = str(tmp_path / "tuning.json")
+        saved = bc.tune_entries()
+        bc.save_tuning(path)
+        bc.tune_clear()
+        assert bc.tune_entries() == [] and bc.schedule(90000, 999) == 256
+        bc.load_tuning(path)
+        assert sorted((e["n"], e["k"], e["wgs"]) for e in bc.tune_entries()) == \
+            sorted((e["n"], e["k"], e["wgs"]) for e in saved)
+        bc.tune_set(90000, 999, 0)                    # removes the bucket's entry
+        assert bc.schedule(90000, 999) == 256 and len(bc.tune_entries()) == 2
+        # argument checks
+        assert lib.bandchol_tune_set(100000, 1000, 1) == -3     # K = 32: no walk
+        assert lib.bandchol_tune_set(1000, 0, 64) == -3         # K = 0: walk only
+        assert lib.bandchol_tune_set(1000, 100, 513) == -3      # above 2 x CUs
+        assert lib.bandchol_tune_set(1000, 100, -1) == -3
+        assert lib.bandchol_tune_set(0, 1, 64) == -1
+        assert lib.bandchol_tune_set(10, -1, 64) == -2
+        assert lib.bandchol_tune_entries(-1, None, None, None, None) == -1
+        assert lib.bandchol_tune_entries(1, None, None, None, None) == -2
+        assert lib.bandchol_tune_entries(0, None, None, None, None) == 2
+        assert lib.bandchol_tune_factor(0, 1, 1, None, None) == -1
+        assert lib.bandchol_tune_factor(10, -1, 1, None, None) == -2
+        assert lib.bandchol_tune_factor(10, 1, 0, None, None) == -3
+        assert lib.bandchol_tune_factor(10, 1, 1001, None, None) == -3
+        with pytest.raises(bc.BandCholError):
+            bc.tune_set(1000, 0, 64)
+    finally:
+        bc.tune_clear()
+        bc.set_walk_limit(prev)
