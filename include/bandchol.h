@@ -118,9 +118,9 @@ int64_t bandchol_set_walk_limit(int64_t kmax);
  * The factor (FP64, FP32, and the wide systems of batch plans when the plan is
  * created) takes, in this order: the walk for K up to the walk limit
  * (bandchol_set_walk_limit; by default K = 0 only), the table entry of the
- * bucket, else the rule w = clamp(8 K rounded up to a multiple of 32, 64,
- * 2 x CUs).  The FP32 factor has no walk and takes the rule where the choice
- * is 1.  The table is process-wide and guarded by a mutex; it starts empty.
+ * bucket, else the rule w = CUs/4 for K <= 16, CUs/2 for K <= 24, CUs for
+ * K <= 55, 2 x CUs above (at least 2).  The FP32 factor has no walk and takes
+ * the rule where the choice is 1.  The table is process-wide and guarded by a mutex; it starts empty.
  *
  * bandchol_schedule: the workgroup count the factor of (n, k) would use now,
  * 0 for n = 0; -1 / -2 for a bad n / k.  No GPU work.

@@ -117,15 +117,19 @@ def test_schedule_rule_and_table_on_host(tmp_path, monkeypatch):
     bc.tune_clear()
     prev = bc.set_walk_limit(0)
     try:
-        # rule: 8 workgroups per tile diagonal, rounded up to 32, within [64, 2 x 256 CUs]
+        # rule: a quarter, half, one or two workgroups per CU (256 CUs) by K
         assert bc.schedule(100000, 0) == 1            # diagonal: the walk
         assert bc.schedule(100000, 50) == 64          # K = 2
-        assert bc.schedule(100000, 500) == 128        # K = 16
+        assert bc.schedule(100000, 500) == 64         # K = 16
+        assert bc.schedule(100000, 520) == 128        # K = 17
+        assert bc.schedule(100000, 768) == 128        # K = 24
+        assert bc.schedule(100000, 769) == 256        # K = 25
         assert bc.schedule(100000, 1000) == 256       # K = 32
-        assert bc.schedule(100000, 1025) == 288       # K = 33: 264 -> 288
-        assert bc.schedule(100000, 1500) == 384       # K = 47: 376 -> 384
+        assert bc.schedule(100000, 1500) == 256       # K = 47
+        assert bc.schedule(100000, 1760) == 256       # K = 55
+        assert bc.schedule(100000, 1761) == 512       # K = 56
         assert bc.schedule(100000, 2000) == 512       # K = 63
-        assert bc.schedule(100000, 99999) == 512      # clamped
+        assert bc.schedule(100000, 99999) == 512
         assert bc.schedule(40, 1000) == 64            # k clipped to n - 1: K = 2
         assert lib.bandchol_schedule(0, 5) == 0
         assert lib.bandchol_schedule(-1, 5) == -1
@@ -139,7 +143,7 @@ def test_schedule_rule_and_table_on_host(tmp_path, monkeypatch):
         assert bc.schedule(100000, 1000) == 384
         assert bc.schedule(70000, 993) == 384         # same bucket (16, 32)
         assert bc.schedule(140000, 1000) == 256       # bucket 17: the rule
-        assert bc.schedule(100000, 1025) == 288       # K = 33: the rule
+        assert bc.schedule(100000, 1025) == 256       # K = 33: the rule
         bc.tune_set(90000, 999, 320)                  # replaces the entry of bucket (16, 32)
         assert bc.tune_entries() == [{"n": 90000, "k": 999, "wgs": 320, "ms": 0.0}]
         bc.tune_set(1000, 480, 1)                     # K = 15: the walk is allowed
