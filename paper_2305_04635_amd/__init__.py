@@ -61,6 +61,10 @@ def load(path=LIB_PATH):
     if _lib is None:
         if not os.path.exists(path):
             raise BandCholError("libbandchol.so is not built (run paper_2305_04635_amd.build.build())")
+        # torch first: its HIP runtime (same soname) then serves the library as
+        # well.  Opened the other way round, the process holds two HIP/HSA
+        # runtimes and the library's finds no device.
+        import torch  # noqa: F401
         lib = ctypes.CDLL(path)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(lib, name)

@@ -66,6 +66,144 @@ __device__ __forceinline__ void tile_trsm_wave(const Band& a, int64_t R, int64_t
   blk_store(a, R, C, 1, 0, o10); blk_store(a, R, C, 1, 1, o11);
 }
 
+// ----------------------------------------------------------------- band as a buffer resource
+
+// The band from column j0 on as a buffer resource.  A buffer load whose offset
+// lies past the resource's size returns zero and such a store is dropped, so
+// the accesses of lanes outside the band (and of idle pipeline slots) go to
+// offset BUF_OOB and need no branch: every load and store is issued, and the
+// compiler can count the outstanding ones exactly.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr int BUF_OOB = 0x7fffffff;
+constexpr int64_t BUF_MAX = 0x7fff0000;   // resource size cap (bytes); offsets stay below it
+
+struct BandBuf {
+  __amdgpu_buffer_rsrc_t rsrc;
+  int64_t n, k, ldab, j0;
+};
+
+// The same value in every lane, held in scalar registers (arguments of a
+// non-inlined function arrive in vector registers; a buffer resource must not).
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ int64_t uni(int64_t x) {
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(uint64_t)x);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ BandBuf band_buf(const Band& a, int64_t j0) {
+  BandBuf b;
+  b.n = uni(a.n), b.k = uni(a.k), b.ldab = uni(a.ldab), b.j0 = uni(j0);
+  const int64_t left = (b.n - b.j0) * b.ldab * (int64_t)sizeof(double);
+  const int64_t base = uni((int64_t)(uintptr_t)(a.ab + j0 * a.ldab));
+  b.rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)(uintptr_t)base, (short)0,
+                                             (int)(left < BUF_MAX ? left : BUF_MAX), 0x00020000);
+  return b;
+}
+
+// Whether every element of the tile columns j0/T .. j0/T + K + 1 lies at a byte
+// offset below BUF_MAX from column j0.
+__device__ __forceinline__ bool band_buf_fits(const Band& a, int K) {
+  return (int64_t)(K + 2) * T * a.ldab * (int64_t)sizeof(double) < BUF_MAX;
+}
+
+// Byte offsets of this lane's accumulator elements of block (bi, bj) of tile
+// (R, C) (BUF_OOB outside the band, or for every lane when !live).
+__device__ __forceinline__ void blk_offsets(const BandBuf& b, int64_t R, int64_t C, int bi, int bj, bool live,
+                                            int (&off)[4]) {
+  const int lane = lane_id();
+  const int64_t i = R * T + 16 * bi + (lane & 15);
+  const int64_t j = C * T + 16 * bj + Prec<double>::acc_col0(lane);
+  const int base = (int)((i - j) + (j - b.j0) * b.ldab);
+  const int step = Prec<double>::ACC_STEP * (int)(b.ldab - 1);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t d = i - j - Prec<double>::ACC_STEP * r;
+    const bool in = live && i < b.n && d >= 0 && d <= b.k;
+    off[r] = in ? (base + step * r) * (int)sizeof(double) : BUF_OOB;
+  }
+}
+
+__device__ __forceinline__ d4 blk_bload(const BandBuf& b, const int (&off)[4]) {
+  d4 v;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    v[r] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(b.rsrc, off[r], 0, 0));
+  return v;
+}
+
+// The elements go through scalars: __builtin_bit_cast applied to a vector
+// element (v[r]) yields element 0 for every r with this compiler.
+__device__ __forceinline__ void blk_bstore(const BandBuf& b, const int (&off)[4], d4 v) {
+  const double e[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const double x = e[r];
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), b.rsrc, off[r], 0, 0);
+  }
+}
+
+// The trailing tiles of one tile column: (dr, dc), 1 <= dc <= dr <= dmax,
+// without (1, 1) (the next diagonal tile's critical update, done in phase C);
+// every third one for wave w (1..3).
+struct TileGen {
+  int dr, dc, idx, dmax, w;
+  __device__ __forceinline__ bool next(int& odr, int& odc) {
+    for (;;) {
+      if (dr > dmax) return false;
+      const int cdr = dr, cdc = dc;
+      if (++dc > dr) dc = 1, ++dr;
+      if (cdr == 1 && cdc == 1) continue;
+      if (idx++ % 3 != w - 1) continue;
+      odr = cdr, odc = cdc;
+      return true;
+    }
+  }
+};
+
+// One tile of the update in flight: its four blocks (acc[bi + 2 bj]) and their
+// element offsets (the upper block of a diagonal tile, and every block of a
+// dead slot, at BUF_OOB).
+struct TileSlot {
+  int dr, dc;
+  bool live;
+  int off[4][4];
+  d4 acc[4];
+};
+
+__device__ __forceinline__ void tile_issue(const BandBuf& b, int64_t Cp, TileGen& gen, TileSlot& s) {
+  s.live = gen.next(s.dr, s.dc);
+  if (!s.live) s.dr = s.dc = 1;
+#pragma unroll
+  for (int blk = 0; blk < 4; ++blk) {
+    const int bi = blk & 1, bj = blk >> 1;
+    blk_offsets(b, Cp + s.dr, Cp + s.dc, bi, bj, s.live && !(s.dr == s.dc && bj > bi), s.off[blk]);
+    s.acc[blk] = blk_bload(b, s.off[blk]);
+  }
+}
+
+// acc[bi + 2 bj] -= X(bi) Y(bj)^T with X, Y the panel tiles (LDS, column-major,
+// pitch LP): per k-step two fragments of each feed four independent MFMAs.
+__device__ __forceinline__ void tile_update(const lds_d* x, const lds_d* y, d4 (&acc)[4]) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int q = 0; q < T / 4; ++q) {
+    const int kk = 4 * q + (lane >> 4);
+    const double x0 = -x[kk * LP + (lane & 15)], x1 = -x[kk * LP + 16 + (lane & 15)];
+    const double y0 = y[kk * LP + (lane & 15)], y1 = y[kk * LP + 16 + (lane & 15)];
+    acc[0] = mfma_xyt(x0, y0, acc[0]);
+    acc[1] = mfma_xyt(x1, y0, acc[1]);
+    acc[2] = mfma_xyt(x0, y1, acc[2]);
+    acc[3] = mfma_xyt(x1, y1, acc[3]);
+  }
+}
+
+__device__ __forceinline__ void tile_finish(const BandBuf& b, const lds_d* pnl, TileSlot& s) {
+  tile_update(pnl + (size_t)(s.dr - 1) * T * LP, pnl + (size_t)(s.dc - 1) * T * LP, s.acc);
+#pragma unroll
+  for (int blk = 0; blk < 4; ++blk) blk_bstore(b, s.off[blk], s.acc[blk]);
+}
+
 struct WalkLds {
   lds_d* diag;    // T*LP
   lds_d* linvt;   // 2 x T*LP (row-major, pitch LP), alternating by column parity
@@ -127,6 +265,24 @@ __device__ __attribute__((noinline)) void walk_column_rest(const Band& a_, int K
   if (lane == 0) __hip_atomic_fetch_add(s_sync, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
   while (__hip_atomic_load(s_sync, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < sync_target)
     __builtin_amdgcn_s_sleep(1);
+  if (band_buf_fits(a, K)) {
+    // whole tiles per wave, the next one's loads in flight while the current
+    // one is on the matrix cores (two slots, alternating)
+    const int64_t Cu = uni(Cp);
+    const BandBuf b = band_buf(a, (Cu + 1) * T);
+    TileGen gen{1, 1, 0, uni((int)(K < NB - 1 - Cu ? K : NB - 1 - Cu)), uni(wave)};
+    TileSlot s0, s1;
+    tile_issue(b, Cu, gen, s0);
+    for (;;) {
+      if (!s0.live) break;
+      tile_issue(b, Cu, gen, s1);
+      tile_finish(b, L.pnl, s0);
+      if (!s1.live) break;
+      tile_issue(b, Cu, gen, s0);
+      tile_finish(b, L.pnl, s1);
+    }
+    return;
+  }
   for (int dr = 1; dr <= K && Cp + dr < NB; ++dr) {
     for (int dc = 1; dc <= dr; ++dc) {
       if (dr == 1 && dc == 1) continue;

@@ -190,6 +190,43 @@ def test_tile_schedule_each_K(K):
         bc.set_walk_limit(prev)
 
 
+@pytest.mark.parametrize("K", range(1, 16))
+def test_walk_each_K(K):
+    """The single-workgroup walk at every tile-diagonal count it takes
+    (1..15): its trailing updates keep eight blocks per wave in flight, in
+    an order that changes with K; n ragged, a few tile rows past K and many;
+    the integer factor must come out bit for bit."""
+    import paper_2305_04635_amd as bc
+    prev = bc.set_walk_limit(15)
+    try:
+        k = 32 * K - 5
+        for n in (32 * (K + 2) + 7, 32 * (3 * K + 6) - 3):
+            print("walk", n, k, flush=True)
+            ab = synth.band_diagdom(n, k, 3 * n + K)
+            check_against_oracle(ab, k, nrhs=1, seed=K)
+            l0 = synth.int_factor(n, k, 13 + K, pow2_max=1)
+            l_gpu, info = gpu_factor(synth.band_ldlt(l0, k), k)
+            assert info == 0 and np.array_equal(l_gpu, l0), (n, k)
+    finally:
+        bc.set_walk_limit(prev)
+
+
+def test_walk_huge_ldab():
+    """A leading dimension so large that the tile columns one step touches
+    span more than 2 GB: the walk takes its per-block path (no buffer
+    resource), with the same result."""
+    import paper_2305_04635_amd as bc
+    prev = bc.set_walk_limit(15)
+    try:
+        n, k, ldab = 33, 32, 2900000
+        l0 = synth.int_factor(n, k, 99, pow2_max=1)
+        a = synth.band_ldlt(l0, k, ldab=ldab)
+        l_gpu, info = gpu_factor(a, k)
+        assert info == 0 and np.array_equal(l_gpu[: k + 1], l0)
+    finally:
+        bc.set_walk_limit(prev)
+
+
 @pytest.mark.parametrize("k", [50, 1000, 2000])
 def test_full_size_sampled(k):
     """The benchmark's size and input recipe (n = 1e5, interior-point-like SPD
