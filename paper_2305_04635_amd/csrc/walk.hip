@@ -27,7 +27,10 @@ namespace bandchol_walk {
 
 using namespace bandchol;
 
-constexpr int NT = 256;
+constexpr int NT = 256;          // batched solves
+constexpr int WALK_WAVES = 8;    // walk: wave 0 sweeps, the others take the tile column's remaining work
+constexpr int UPD_WAVES = WALK_WAVES - 1;
+constexpr int WALK_NT = 64 * WALK_WAVES;
 
 // ----------------------------------------------------------------- tile helpers
 
@@ -145,7 +148,7 @@ __device__ __forceinline__ void blk_bstore(const BandBuf& b, const int (&off)[4]
 
 // The trailing tiles of one tile column: (dr, dc), 1 <= dc <= dr <= dmax,
 // without (1, 1) (the next diagonal tile's critical update, done in phase C);
-// every third one for wave w (1..3).
+// every UPD_WAVES-th one for wave w (1..UPD_WAVES).
 struct TileGen {
   int dr, dc, idx, dmax, w;
   __device__ __forceinline__ bool next(int& odr, int& odc) {
@@ -154,7 +157,7 @@ struct TileGen {
       const int cdr = dr, cdc = dc;
       if (++dc > dr) dc = 1, ++dr;
       if (cdr == 1 && cdc == 1) continue;
-      if (idx++ % 3 != w - 1) continue;
+      if (idx++ % UPD_WAVES != w - 1) continue;
       odr = cdr, odc = cdc;
       return true;
     }
@@ -198,16 +201,73 @@ __device__ __forceinline__ void tile_update(const lds_d* x, const lds_d* y, d4 (
   }
 }
 
-__device__ __forceinline__ void tile_finish(const BandBuf& b, const lds_d* pnl, TileSlot& s) {
+__device__ __forceinline__ void tile_finish(const BandBuf& b, const lds_d* pnl, lds_d* stB, lds_d* stC,
+                                            TileSlot& s) {
   tile_update(pnl + (size_t)(s.dr - 1) * T * LP, pnl + (size_t)(s.dc - 1) * T * LP, s.acc);
+  lds_d* st = s.dr == 2 ? (s.dc == 1 ? stB : stC) : nullptr;
+  if (st) {
+#pragma unroll
+    for (int blk = 0; blk < 4; ++blk) blk_to_lds(st, blk & 1, blk >> 1, s.acc[blk]);
+    return;
+  }
 #pragma unroll
   for (int blk = 0; blk < 4; ++blk) blk_bstore(b, s.off[blk], s.acc[blk]);
 }
+
+// One panel tile (Cp + d, Cp) of the column's trsm in flight: both row-blocks
+// of its current value, x[bi][q] = A(R*T + 16 bi + l%16, Cp*T + 4q + l/16).
+struct PanelSlot {
+  int d;
+  bool live;
+  double x[2][T / 4];
+};
+
+__device__ __forceinline__ void panel_issue(const BandBuf& b, int64_t Cp, int d, int dmax, PanelSlot& s) {
+  const int lane = lane_id();
+  s.live = d <= dmax;
+  s.d = s.live ? d : 2;
+  const int64_t j = Cp * T + (lane >> 4);
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi) {
+    const int64_t i = (Cp + s.d) * T + 16 * bi + (lane & 15);
+    const int base = (int)((i - j) + (j - b.j0) * b.ldab);
+#pragma unroll
+    for (int q = 0; q < T / 4; ++q) {
+      const int64_t dd = i - j - 4 * q;
+      const bool in = s.live && i < b.n && dd >= 0 && dd <= b.k;
+      const int off = in ? (base + 4 * q * (int)(b.ldab - 1)) * (int)sizeof(double) : BUF_OOB;
+      s.x[bi][q] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(b.rsrc, off, 0, 0));
+    }
+  }
+}
+
+// L(Cp + d, Cp) = tile * L(Cp,Cp)^{-T}: into the panel's LDS slot d-1 and back
+// to the band.
+__device__ __forceinline__ void panel_finish(const BandBuf& b, int64_t Cp, const lds_d* linvt, lds_d* pnl,
+                                             PanelSlot& s) {
+  lds_d* out = pnl + (size_t)(s.d - 1) * T * LP;
+#pragma unroll
+  for (int blk = 0; blk < 4; ++blk) {
+    const int bi = blk & 1, bj = blk >> 1;
+    const d4 o = blk_trsm_frag(s.x[bi], linvt, bj);
+    blk_to_lds(out, bi, bj, o);
+    int off[4];
+    blk_offsets(b, Cp + s.d, Cp, bi, bj, s.live, off);
+    blk_bstore(b, off, o);
+  }
+}
+
+// Up to this many tile diagonals the LDS also holds two staging tiles: the
+// next step's tiles (C+1, C) and (C+1, C+1) stay there after their last update
+// instead of a round trip through the band.
+constexpr int STAGE_KMAX = 13;
 
 struct WalkLds {
   lds_d* diag;    // T*LP
   lds_d* linvt;   // 2 x T*LP (row-major, pitch LP), alternating by column parity
   lds_d* pnl;     // K x T*LP
+  lds_d* stB;     // T*LP: tile (C+1, C) before its trsm (null past STAGE_KMAX)
+  lds_d* stC;     // T*LP: tile (C+1, C+1) before its last update (null past STAGE_KMAX)
 };
 
 __device__ __forceinline__ WalkLds walk_lds(lds_d* base, int K) {
@@ -215,9 +275,15 @@ __device__ __forceinline__ WalkLds walk_lds(lds_d* base, int K) {
   L.diag = base;
   L.linvt = L.diag + T * LP;
   L.pnl = L.linvt + 2 * T * LP;
-  (void)K;
+  L.stB = K <= STAGE_KMAX ? L.pnl + (size_t)K * T * LP : nullptr;
+  L.stC = K <= STAGE_KMAX ? L.stB + T * LP : nullptr;
   return L;
 }
+
+// Whether this step's phase-A update leaves tiles (C+1, C) and (C+1, C+1) in
+// the staging tiles: there is LDS for them, the update runs on the buffer path,
+// and both tiles lie inside the band of the column updated (K >= 2).
+__device__ __forceinline__ bool walk_staged(const WalkLds& L, const Band& a, int K);
 
 // ----------------------------------------------------------------- the walk
 //
@@ -257,39 +323,58 @@ __device__ __attribute__((noinline)) void walk_column_rest(const Band& a_, int K
   const Band a = a_;
   const WalkLds L = L_;
   const int wave = wave_id(), lane = lane_id();
+  if (band_buf_fits(a, K)) {
+    const int64_t Cu = uni(Cp);
+    const int dmax = uni((int)(K < NB - 1 - Cu ? K : NB - 1 - Cu));
+    const BandBuf bp = band_buf(a, Cu * T);         // the panel's tile column
+    const BandBuf b = band_buf(a, (Cu + 1) * T);    // the trailing tile columns
+    TileGen gen{1, 1, 0, dmax, uni(wave)};
+    TileSlot s0, s1;
+    tile_issue(b, Cu, gen, s0);   // independent of the panel: its loads go out first
+    // the panel tiles (Cp + d, Cp), d = 2 .. dmax, every UPD_WAVES-th for this wave, two in flight
+    int d = 1 + uni(wave);
+    PanelSlot p0, p1;
+    panel_issue(bp, Cu, d, dmax, p0);
+    for (;;) {
+      if (!p0.live) break;
+      panel_issue(bp, Cu, d += UPD_WAVES, dmax, p1);
+      panel_finish(bp, Cu, lt_prev, L.pnl, p0);
+      if (!p1.live) break;
+      panel_issue(bp, Cu, d += UPD_WAVES, dmax, p0);
+      panel_finish(bp, Cu, lt_prev, L.pnl, p1);
+    }
+    // waves 1-3 meet before using each other's panel tiles
+    __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): this wave's LDS writes are done
+    if (lane == 0) __hip_atomic_fetch_add(s_sync, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    while (__hip_atomic_load(s_sync, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < sync_target)
+      __builtin_amdgcn_s_sleep(1);
+    // whole tiles per wave, the next one's loads in flight while the current
+    // one is on the matrix cores (two slots, alternating)
+    for (;;) {
+      if (!s0.live) break;
+      tile_issue(b, Cu, gen, s1);
+      tile_finish(b, L.pnl, L.stB, L.stC, s0);
+      if (!s1.live) break;
+      tile_issue(b, Cu, gen, s0);
+      tile_finish(b, L.pnl, L.stB, L.stC, s1);
+    }
+    return;
+  }
   for (int d = 2; d <= K && Cp + d < NB; ++d)
-    if ((d - 2) % 3 == wave - 1) tile_trsm_wave(a, Cp + d, Cp, lt_prev, L.pnl + (size_t)(d - 1) * T * LP);
+    if ((d - 2) % UPD_WAVES == wave - 1) tile_trsm_wave(a, Cp + d, Cp, lt_prev, L.pnl + (size_t)(d - 1) * T * LP);
   int idx = 0;
   // waves 1-3 meet before using each other's panel tiles
   __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): this wave's LDS writes are done
   if (lane == 0) __hip_atomic_fetch_add(s_sync, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
   while (__hip_atomic_load(s_sync, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < sync_target)
     __builtin_amdgcn_s_sleep(1);
-  if (band_buf_fits(a, K)) {
-    // whole tiles per wave, the next one's loads in flight while the current
-    // one is on the matrix cores (two slots, alternating)
-    const int64_t Cu = uni(Cp);
-    const BandBuf b = band_buf(a, (Cu + 1) * T);
-    TileGen gen{1, 1, 0, uni((int)(K < NB - 1 - Cu ? K : NB - 1 - Cu)), uni(wave)};
-    TileSlot s0, s1;
-    tile_issue(b, Cu, gen, s0);
-    for (;;) {
-      if (!s0.live) break;
-      tile_issue(b, Cu, gen, s1);
-      tile_finish(b, L.pnl, s0);
-      if (!s1.live) break;
-      tile_issue(b, Cu, gen, s0);
-      tile_finish(b, L.pnl, s1);
-    }
-    return;
-  }
   for (int dr = 1; dr <= K && Cp + dr < NB; ++dr) {
     for (int dc = 1; dc <= dr; ++dc) {
       if (dr == 1 && dc == 1) continue;
       for (int blk = 0; blk < 4; ++blk) {
         const int bi = blk & 1, bj = blk >> 1;
         if (dr == dc && bj > bi) continue;
-        if (idx++ % 3 != wave - 1) continue;
+        if (idx++ % UPD_WAVES != wave - 1) continue;
         d4 acc = blk_load(a, Cp + dr, Cp + dc, bi, bj);
         acc = blk_gemm_lds(L.pnl + (size_t)(dr - 1) * T * LP, L.pnl + (size_t)(dc - 1) * T * LP, bi, bj, acc);
         blk_store(a, Cp + dr, Cp + dc, bi, bj, acc);
@@ -311,18 +396,23 @@ __device__ __forceinline__ void store_linvt(const lds_d* lt, glb_d* dst) {
   for (int p = 0; p < T / 2; ++p) dst[64 * p + lane] = v[p];
 }
 
+__device__ __forceinline__ bool walk_staged(const WalkLds& L, const Band& a, int K) {
+  return L.stB != nullptr && K >= 2 && band_buf_fits(a, K);
+}
+
 // Returns info (0 or the 1-based failing column).  linv: if not null, receives
 // L(C,C)^{-T} (row-major T x T) for every tile column C.
 __device__ int64_t walk_factor(const Band a, const int K, const WalkLds L, double* linv, lds_i* s_fail,
                                lds_i* s_sync) {
   const int wave = wave_id();
   const int64_t NB = (a.n + T - 1) / T;
+  const bool staged = walk_staged(L, a, K);
   if (threadIdx.x == 0) { *s_fail = -1; *s_sync = 0; }
   // stage tile (0, 0)
-  if (wave >= 1) {
+  if (wave >= 1 && wave <= 3) {
     const int bi = (wave >= 2), bj = (wave == 3);
     blk_to_lds(L.diag, bi, bj, blk_load(a, 0, 0, bi, bj));
-  } else {
+  } else if (wave == 0) {
     blk_to_lds(L.diag, 0, 1, d4{0, 0, 0, 0});
   }
   __syncthreads();
@@ -332,7 +422,7 @@ __device__ int64_t walk_factor(const Band a, const int K, const WalkLds L, doubl
     const lds_d* lt_prev = L.linvt + ((C + 1) & 1) * T * LP;
     // ---------------- phase A
     if (wave == 0) walk_sweep(a, C, L, lt, s_fail);
-    else if (C >= 1) walk_column_rest(a, K, NB, C - 1, L, lt_prev, s_sync, sync_target += 3);
+    else if (C >= 1) walk_column_rest(a, K, NB, C - 1, L, lt_prev, s_sync, sync_target += UPD_WAVES);
     wait_vmem();
     __syncthreads();
     if (*s_fail >= 0) return C * T + *s_fail + 1;
@@ -340,26 +430,50 @@ __device__ int64_t walk_factor(const Band a, const int K, const WalkLds L, doubl
       if (linv && wave == 0) store_linvt(lt, (glb_d*)linv + C * T * T);
       break;
     }
-    // ---------------- phase B: trsm of tile (C+1, C)
+    // ---------------- phase B: trsm of tile (C+1, C), one block per wave 0-3
+    const bool from_lds = staged && C >= 1;   // phase A of this step left (C+1, C) and (C+1, C+1) in LDS
     if (K >= 1) {
-      const int bi = wave & 1, bj = wave >> 1;
+      const bool mine = wave < 4;
+      const int bi = wave & 1, bj = (wave >> 1) & 1;
       double x[T / 4];
-      rowblk_load(a, C + 1, C, bi, x);
+      if (mine) {
+        if (from_lds) {
+          const int lane = lane_id();
+#pragma unroll
+          for (int q = 0; q < T / 4; ++q) x[q] = L.stB[(4 * q + (lane >> 4)) * LP + 16 * bi + (lane & 15)];
+        } else {
+          rowblk_load(a, C + 1, C, bi, x);
+        }
+      }
       wait_vmem();
       __syncthreads();   // every wave holds its input before any output is written
-      const d4 out = blk_trsm_frag(x, lt, bj);
-      blk_to_lds(L.pnl, bi, bj, out);
-      blk_store(a, C + 1, C, bi, bj, out);
+      if (mine) {
+        const d4 out = blk_trsm_frag(x, lt, bj);
+        blk_to_lds(L.pnl, bi, bj, out);
+        blk_store(a, C + 1, C, bi, bj, out);
+      }
     }
     wait_vmem();
     __syncthreads();
     // ---------------- phase C: stage tile (C+1, C+1) minus the critical update
-    if (wave >= 1) {
+    if (wave >= 1 && wave <= 3) {
       const int bi = (wave >= 2), bj = (wave == 3);
-      d4 acc = blk_load(a, C + 1, C + 1, bi, bj);
+      d4 acc;
+      if (from_lds) {
+        acc = blk_from_lds(L.stC, bi, bj);
+        // rows past n: the identity, as blk_load gives
+        const int lane = lane_id();
+        const int64_t i = (C + 1) * T + 16 * bi + (lane & 15);
+        const int64_t j = (C + 1) * T + 16 * bj + Prec<double>::acc_col0(lane);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (i >= a.n && i == j + Prec<double>::ACC_STEP * r) acc[r] = 1.0;
+      } else {
+        acc = blk_load(a, C + 1, C + 1, bi, bj);
+      }
       if (K >= 1) acc = blk_gemm_lds(L.pnl, L.pnl, bi, bj, acc);
       blk_to_lds(L.diag, bi, bj, acc);
-    } else {
+    } else if (wave == 0) {
       blk_to_lds(L.diag, 0, 1, d4{0, 0, 0, 0});
       if (linv) store_linvt(lt, (glb_d*)linv + C * T * T);
     }
@@ -368,7 +482,7 @@ __device__ int64_t walk_factor(const Band a, const int K, const WalkLds L, doubl
   return 0;
 }
 
-__global__ void __launch_bounds__(NT) walk_single_kernel(WalkSys w, int K, int64_t* info) {
+__global__ void __launch_bounds__(WALK_NT) walk_single_kernel(WalkSys w, int K, int64_t* info) {
   extern __shared__ double lds_dyn[];
   __shared__ int s_fail, s_sync;
   const Band a{(glb_d*)w.ab, w.n, w.k, w.ldab};
@@ -377,7 +491,7 @@ __global__ void __launch_bounds__(NT) walk_single_kernel(WalkSys w, int K, int64
 }
 
 // Batched factor: systems sys[order[t]] for t = 0, 1, ... taken from *queue.
-__global__ void __launch_bounds__(NT) walk_batch_kernel(const WalkSys* sys, const int* order, int nsys, int Kmax,
+__global__ void __launch_bounds__(WALK_NT) walk_batch_kernel(const WalkSys* sys, const int* order, int nsys, int Kmax,
                                                         unsigned* queue, int64_t* info) {
   extern __shared__ double lds_dyn[];
   __shared__ int s_idx, s_fail, s_sync;
@@ -537,7 +651,9 @@ __global__ void batch_clear_kernel(unsigned* queue, int count) {
 
 using namespace bandchol_walk;
 
-size_t bandchol_walk_lds_bytes(int K) { return sizeof(double) * ((size_t)T * LP + 2 * T * LP + (size_t)K * T * LP); }
+size_t bandchol_walk_lds_bytes(int K) {
+  return sizeof(double) * ((size_t)(3 + K + (K <= STAGE_KMAX ? 2 : 0)) * T * LP);
+}
 
 size_t bandchol_solve_batch_lds_bytes(int Kmax) {
   return sizeof(double) * ((size_t)4 * T * RHS_PASS + (size_t)(Kmax + 1) * T * RHS_PASS);
@@ -564,7 +680,7 @@ hipError_t bandchol_walk_single_launch(const WalkSys& w, int K, int64_t* d_info,
   const size_t lds = bandchol_walk_lds_bytes(K);
   hipError_t e = set_lds_attr((const void*)walk_single_kernel, lds);
   if (e != hipSuccess) return e;
-  walk_single_kernel<<<1, NT, lds, st>>>(w, K, d_info);
+  walk_single_kernel<<<1, WALK_NT, lds, st>>>(w, K, d_info);
   return hipGetLastError();
 }
 
@@ -574,7 +690,7 @@ hipError_t bandchol_walk_batch_factor_launch(const WalkSys* d_sys, const int* d_
   hipError_t e = set_lds_attr((const void*)walk_batch_kernel, lds);
   if (e != hipSuccess) return e;
   batch_clear_kernel<<<1, 64, 0, st>>>(d_queue, 1);
-  walk_batch_kernel<<<grid, NT, lds, st>>>(d_sys, d_order, nsys, Kmax, d_queue, d_info);
+  walk_batch_kernel<<<grid, WALK_NT, lds, st>>>(d_sys, d_order, nsys, Kmax, d_queue, d_info);
   return hipGetLastError();
 }
 
