@@ -41,6 +41,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (vector = matrix)
+# the pivot chain's floor: one wave sweeps a 32-column diagonal tile in about 9160
+# cycles (measured on gfx950 with s_memtime, tile in isolation), at 2.4 GHz
+SWEEP_TILE_S = 9160 / 2.4e9
 PEAK_HBM_GBS = 8000.0
 DEFAULT_KS = (50, 100, 250, 500, 1000, 2000)
 
@@ -198,6 +201,24 @@ def main():
         print("bench.py: factorization failed, info per k = %s" % infos, file=sys.stderr)
         sys.exit(1)
 
+    # cold factor (after the timed region): the band restored, then 1 GiB written
+    # through the caches (more than the 256 MB Infinity Cache), then the factor alone
+    scrub = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+    cold_ms = []
+    for m in mats:
+        ts = []
+        for r in range(3):
+            m["ab"].copy_(m["ab0"])
+            scrub.fill_(float(r))
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            bc.factor_async(m["ab"], n, m["k"], m["info"])
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        cold_ms.append(float(np.median(ts)))
+    del scrub
+
     ms_step = (t1 - t0) * 1e3 / args.steps
     per_k = []
     for i, m in enumerate(mats):
@@ -208,7 +229,9 @@ def main():
                       "solve_ms": round(s_ms, 4),
                       "factor_gflops": round(ff / (f_ms * 1e-3) / 1e9, 2),
                       "factor_frac_fp64_peak": round(ff / (f_ms * 1e-3) / (PEAK_FP64_TFLOPS * 1e12), 5),
-                      "factor_frac_hbm": round(16.0 * n * (m["k"] + 1) / (f_ms * 1e-3) / (PEAK_HBM_GBS * 1e9), 5)})
+                      "factor_frac_hbm": round(16.0 * n * (m["k"] + 1) / (f_ms * 1e-3) / (PEAK_HBM_GBS * 1e9), 5),
+                      "factor_frac_chain": round(((n + 31) // 32) * SWEEP_TILE_S / (f_ms * 1e-3), 4),
+                      "factor_ms_cold": round(cold_ms[i], 4)})
 
     step_flops = sum(factor_flops(n, k) + solve_flops(n, k, nrhs) for k in ks)
     value = step_flops / (ms_step * 1e-3) / 1e9
