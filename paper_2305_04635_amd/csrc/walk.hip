@@ -317,7 +317,7 @@ __device__ __attribute__((noinline)) void walk_sweep(const Band& a_, int64_t C, 
 }
 
 // waves 1-3: the rest of tile column Cp (trsm of d >= 2, then all updates but the critical one)
-__device__ __attribute__((noinline)) void walk_column_rest(const Band& a_, int K, int64_t NB, int64_t Cp,
+__device__ __forceinline__ void walk_column_rest(const Band& a_, int K, int64_t NB, int64_t Cp,
                                                            const WalkLds& L_, const lds_d* lt_prev, lds_i* s_sync,
                                                            int sync_target) {
   const Band a = a_;
@@ -400,45 +400,78 @@ __device__ __forceinline__ bool walk_staged(const WalkLds& L, const Band& a, int
   return L.stB != nullptr && K >= 2 && band_buf_fits(a, K);
 }
 
-// Returns info (0 or the 1-based failing column).  linv: if not null, receives
-// L(C,C)^{-T} (row-major T x T) for every tile column C.
-__device__ int64_t walk_factor(const Band a, const int K, const WalkLds L, double* linv, lds_i* s_fail,
-                               lds_i* s_sync) {
-  const int wave = wave_id();
+// The step loop of each wave role, one function per role with the phase work
+// inlined (a call inside the loop would save and restore registers around it on
+// every step).  Both roles pass the same barriers: after phase A, inside phase
+// B (K >= 1), after phase B and after phase C.  They return the tile column
+// whose sweep failed (the column inside it in *s_fail), or -1.
+__device__ __attribute__((noinline)) int64_t walk_wave0(const Band& a_, int K, const WalkLds& L_, double* linv,
+                                                       lds_i* s_fail, bool staged) {
+  const Band a = a_;
+  const WalkLds L = L_;
   const int64_t NB = (a.n + T - 1) / T;
-  const bool staged = walk_staged(L, a, K);
-  if (threadIdx.x == 0) { *s_fail = -1; *s_sync = 0; }
-  // stage tile (0, 0)
-  if (wave >= 1 && wave <= 3) {
-    const int bi = (wave >= 2), bj = (wave == 3);
-    blk_to_lds(L.diag, bi, bj, blk_load(a, 0, 0, bi, bj));
-  } else if (wave == 0) {
+  const int lane = lane_id();
+  for (int64_t C = 0; C < NB; ++C) {
+    lds_d* lt = L.linvt + (C & 1) * T * LP;
+    // ---------------- phase A: sweep of the staged diagonal tile
+    walk_sweep(a, C, L, lt, s_fail);
+    wait_vmem();
+    __syncthreads();
+    if (*s_fail >= 0) return C;
+    if (C + 1 >= NB) {
+      if (linv) store_linvt(lt, (glb_d*)linv + C * T * T);
+      break;
+    }
+    // ---------------- phase B: block (0, 0) of the trsm of tile (C+1, C)
+    const bool from_lds = staged && C >= 1;
+    if (K >= 1) {
+      double x[T / 4];
+      if (from_lds) {
+#pragma unroll
+        for (int q = 0; q < T / 4; ++q) x[q] = L.stB[(4 * q + (lane >> 4)) * LP + (lane & 15)];
+      } else {
+        rowblk_load(a, C + 1, C, 0, x);
+      }
+      wait_vmem();
+      __syncthreads();
+      const d4 out = blk_trsm_frag(x, lt, 0);
+      blk_to_lds(L.pnl, 0, 0, out);
+      blk_store(a, C + 1, C, 0, 0, out);
+    }
+    wait_vmem();
+    __syncthreads();
+    // ---------------- phase C: the upper block of the next diagonal tile, L(C,C)^{-T} out
     blk_to_lds(L.diag, 0, 1, d4{0, 0, 0, 0});
+    if (linv) store_linvt(lt, (glb_d*)linv + C * T * T);
+    __syncthreads();
   }
-  __syncthreads();
+  return -1;
+}
+
+__device__ __attribute__((noinline)) int64_t walk_waves(const Band& a_, int K, const WalkLds& L_, lds_i* s_fail,
+                                                       lds_i* s_sync, bool staged) {
+  const Band a = a_;
+  const WalkLds L = L_;
+  const int64_t NB = (a.n + T - 1) / T;
+  const int wave = wave_id(), lane = lane_id();
   int sync_target = 0;
   for (int64_t C = 0; C < NB; ++C) {
     lds_d* lt = L.linvt + (C & 1) * T * LP;
     const lds_d* lt_prev = L.linvt + ((C + 1) & 1) * T * LP;
-    // ---------------- phase A
-    if (wave == 0) walk_sweep(a, C, L, lt, s_fail);
-    else if (C >= 1) walk_column_rest(a, K, NB, C - 1, L, lt_prev, s_sync, sync_target += UPD_WAVES);
+    // ---------------- phase A: the rest of tile column C-1
+    if (C >= 1) walk_column_rest(a, K, NB, C - 1, L, lt_prev, s_sync, sync_target += UPD_WAVES);
     wait_vmem();
     __syncthreads();
-    if (*s_fail >= 0) return C * T + *s_fail + 1;
-    if (C + 1 >= NB) {
-      if (linv && wave == 0) store_linvt(lt, (glb_d*)linv + C * T * T);
-      break;
-    }
-    // ---------------- phase B: trsm of tile (C+1, C), one block per wave 0-3
-    const bool from_lds = staged && C >= 1;   // phase A of this step left (C+1, C) and (C+1, C+1) in LDS
+    if (*s_fail >= 0) return C;
+    if (C + 1 >= NB) break;
+    // ---------------- phase B: blocks of the trsm of tile (C+1, C), one per wave 1-3
+    const bool from_lds = staged && C >= 1;
     if (K >= 1) {
       const bool mine = wave < 4;
       const int bi = wave & 1, bj = (wave >> 1) & 1;
       double x[T / 4];
       if (mine) {
         if (from_lds) {
-          const int lane = lane_id();
 #pragma unroll
           for (int q = 0; q < T / 4; ++q) x[q] = L.stB[(4 * q + (lane >> 4)) * LP + 16 * bi + (lane & 15)];
         } else {
@@ -456,13 +489,12 @@ __device__ int64_t walk_factor(const Band a, const int K, const WalkLds L, doubl
     wait_vmem();
     __syncthreads();
     // ---------------- phase C: stage tile (C+1, C+1) minus the critical update
-    if (wave >= 1 && wave <= 3) {
+    if (wave <= 3) {
       const int bi = (wave >= 2), bj = (wave == 3);
       d4 acc;
       if (from_lds) {
         acc = blk_from_lds(L.stC, bi, bj);
         // rows past n: the identity, as blk_load gives
-        const int lane = lane_id();
         const int64_t i = (C + 1) * T + 16 * bi + (lane & 15);
         const int64_t j = (C + 1) * T + 16 * bj + Prec<double>::acc_col0(lane);
 #pragma unroll
@@ -473,13 +505,29 @@ __device__ int64_t walk_factor(const Band a, const int K, const WalkLds L, doubl
       }
       if (K >= 1) acc = blk_gemm_lds(L.pnl, L.pnl, bi, bj, acc);
       blk_to_lds(L.diag, bi, bj, acc);
-    } else if (wave == 0) {
-      blk_to_lds(L.diag, 0, 1, d4{0, 0, 0, 0});
-      if (linv) store_linvt(lt, (glb_d*)linv + C * T * T);
     }
     __syncthreads();
   }
-  return 0;
+  return -1;
+}
+
+// Returns info (0 or the 1-based failing column).  linv: if not null, receives
+// L(C,C)^{-T} (row-major T x T) for every tile column C.
+__device__ int64_t walk_factor(const Band a, const int K, const WalkLds L, double* linv, lds_i* s_fail,
+                               lds_i* s_sync) {
+  const int wave = wave_id();
+  const bool staged = walk_staged(L, a, K);
+  if (threadIdx.x == 0) { *s_fail = -1; *s_sync = 0; }
+  // stage tile (0, 0)
+  if (wave >= 1 && wave <= 3) {
+    const int bi = (wave >= 2), bj = (wave == 3);
+    blk_to_lds(L.diag, bi, bj, blk_load(a, 0, 0, bi, bj));
+  } else if (wave == 0) {
+    blk_to_lds(L.diag, 0, 1, d4{0, 0, 0, 0});
+  }
+  __syncthreads();
+  const int64_t Cf = wave == 0 ? walk_wave0(a, K, L, linv, s_fail, staged) : walk_waves(a, K, L, s_fail, s_sync, staged);
+  return Cf >= 0 ? Cf * T + *s_fail + 1 : 0;
 }
 
 __global__ void __launch_bounds__(WALK_NT) walk_single_kernel(WalkSys w, int K, int64_t* info) {
