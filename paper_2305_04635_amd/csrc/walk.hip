@@ -587,6 +587,23 @@ __device__ void solve_one(const Band& a, int K, const glb_d* linv, glb_d* b, int
   const int64_t NB = (a.n + T - 1) / T;
   for (int64_t it = 0; it < NB; ++it) {
     const int64_t R = FWD ? it : NB - 1 - it;
+    // wave 0: this block's row of L(R,R)^{-T} (or of its transpose) and b, loaded
+    // before its share of the tiles, so that they are in registers when the
+    // partial sums have met (none of them depends on the chain)
+    const int64_t gi = R * T + i;
+    double ltr[T], bv[RH];
+    if (wave == 0) {
+      const glb_d* lt = linv + R * T * T;
+#pragma unroll
+      for (int c = 0; c < T; ++c) ltr[c] = FWD ? lt[c * T + i] : lt[i * T + c];
+      const int64_t gic = gi < a.n ? gi : a.n - 1;
+#pragma unroll
+      for (int t = 0; t < RH; ++t) {
+        const int r = h * RH + t;
+        const double v = b[(r0 + (r < nr ? r : 0)) * ldb + gic];
+        bv[t] = (gi < a.n && r < nr) ? v : 0.0;
+      }
+    }
     double acc[RH];
 #pragma unroll
     for (int t = 0; t < RH; ++t) acc[t] = 0.0;
@@ -622,12 +639,11 @@ __device__ void solve_one(const Band& a, int K, const glb_d* linv, glb_d* b, int
     __syncthreads();
     if (wave == 0) {
       // s = b_R - sum of the partials (row i, this lane's right-hand sides)
-      const int64_t gi = R * T + i;
       double s[RH];
 #pragma unroll
       for (int t = 0; t < RH; ++t) {
         const int r = h * RH + t;
-        double v = (gi < a.n && r < nr) ? b[(r0 + r) * ldb + gi] : 0.0;
+        double v = bv[t];
 #pragma unroll
         for (int w = 0; w < 4; ++w) v -= part[(w * T + i) * RHS_PASS + r];
         s[t] = v;
@@ -640,16 +656,13 @@ __device__ void solve_one(const Band& a, int K, const glb_d* linv, glb_d* b, int
       __builtin_amdgcn_s_waitcnt(0xC07F);
       __builtin_amdgcn_wave_barrier();
       // y_i = sum_c Linv(i, c) s_c = sum_c linvt[c][i] s_c;  x_i = sum_c Linv(c, i) s_c = sum_c linvt[i][c] s_c
-      const glb_d* lt = linv + R * T * T;
       double y[RH];
 #pragma unroll
       for (int t = 0; t < RH; ++t) y[t] = 0.0;
-#pragma unroll 8
-      for (int c = 0; c < T; ++c) {
-        const double l = FWD ? lt[c * T + i] : lt[i * T + c];
 #pragma unroll
-        for (int t = 0; t < RH; ++t) y[t] = fma(l, sbuf[c * RHS_PASS + h * RH + t], y[t]);
-      }
+      for (int c = 0; c < T; ++c)
+#pragma unroll
+        for (int t = 0; t < RH; ++t) y[t] = fma(ltr[c], sbuf[c * RHS_PASS + h * RH + t], y[t]);
       lds_d* yr = ring_at(ring, R, K);
 #pragma unroll
       for (int t = 0; t < RH; ++t) {
