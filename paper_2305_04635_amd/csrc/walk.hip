@@ -330,7 +330,6 @@ __device__ __forceinline__ void walk_column_rest(const Band& a_, int K, int64_t 
     const BandBuf b = band_buf(a, (Cu + 1) * T);    // the trailing tile columns
     TileGen gen{1, 1, 0, dmax, uni(wave)};
     TileSlot s0, s1;
-    tile_issue(b, Cu, gen, s0);   // independent of the panel: its loads go out first
     // the panel tiles (Cp + d, Cp), d = 2 .. dmax, every UPD_WAVES-th for this wave, two in flight
     int d = 1 + uni(wave);
     PanelSlot p0, p1;
@@ -343,7 +342,10 @@ __device__ __forceinline__ void walk_column_rest(const Band& a_, int K, int64_t 
       panel_issue(bp, Cu, d += UPD_WAVES, dmax, p0);
       panel_finish(bp, Cu, lt_prev, L.pnl, p1);
     }
-    // waves 1-3 meet before using each other's panel tiles
+    // the first update tile's loads after the panel work: issued earlier they
+    // kept 48 more registers live through it and the panel loop spilled
+    tile_issue(b, Cu, gen, s0);
+    // waves 1-7 meet before using each other's panel tiles
     __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): this wave's LDS writes are done
     if (lane == 0) __hip_atomic_fetch_add(s_sync, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     while (__hip_atomic_load(s_sync, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < sync_target)
@@ -363,7 +365,7 @@ __device__ __forceinline__ void walk_column_rest(const Band& a_, int K, int64_t 
   for (int d = 2; d <= K && Cp + d < NB; ++d)
     if ((d - 2) % UPD_WAVES == wave - 1) tile_trsm_wave(a, Cp + d, Cp, lt_prev, L.pnl + (size_t)(d - 1) * T * LP);
   int idx = 0;
-  // waves 1-3 meet before using each other's panel tiles
+  // waves 1-7 meet before using each other's panel tiles
   __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): this wave's LDS writes are done
   if (lane == 0) __hip_atomic_fetch_add(s_sync, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
   while (__hip_atomic_load(s_sync, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < sync_target)
