@@ -214,7 +214,7 @@ __device__ __forceinline__ void tile_finish(const BandBuf& b, const lds_d* pnl, 
   for (int blk = 0; blk < 4; ++blk) blk_bstore(b, s.off[blk], s.acc[blk]);
 }
 
-// One panel tile (Cp + d, Cp) of the column's trsm in flight: both row-blocks
+// One panel tile (Cp + d, Cp) of the column's trsm: both row-blocks
 // of its current value, x[bi][q] = A(R*T + 16 bi + l%16, Cp*T + 4q + l/16).
 struct PanelSlot {
   int d;
@@ -330,17 +330,12 @@ __device__ __forceinline__ void walk_column_rest(const Band& a_, int K, int64_t 
     const BandBuf b = band_buf(a, (Cu + 1) * T);    // the trailing tile columns
     TileGen gen{1, 1, 0, dmax, uni(wave)};
     TileSlot s0, s1;
-    // the panel tiles (Cp + d, Cp), d = 2 .. dmax, every UPD_WAVES-th for this wave, two in flight
-    int d = 1 + uni(wave);
-    PanelSlot p0, p1;
-    panel_issue(bp, Cu, d, dmax, p0);
-    for (;;) {
-      if (!p0.live) break;
-      panel_issue(bp, Cu, d += UPD_WAVES, dmax, p1);
+    // the panel tiles (Cp + d, Cp), d = 2 .. dmax, every UPD_WAVES-th for this
+    // wave, one at a time (a second one in flight cost more in spills than it hid)
+    for (int d = 1 + uni(wave); d <= dmax; d += UPD_WAVES) {
+      PanelSlot p0;
+      panel_issue(bp, Cu, d, dmax, p0);
       panel_finish(bp, Cu, lt_prev, L.pnl, p0);
-      if (!p1.live) break;
-      panel_issue(bp, Cu, d += UPD_WAVES, dmax, p0);
-      panel_finish(bp, Cu, lt_prev, L.pnl, p1);
     }
     // the first update tile's loads after the panel work: issued earlier they
     // kept 48 more registers live through it and the panel loop spilled
