@@ -611,7 +611,9 @@ __device__ void solve_one(const Band& a, int K, const glb_d* linv, glb_d* b, int
       if (FWD) {
         // row i of tile (R, S): A(R*T + i, S*T + j), j = 0..T-1
         const Run run = band_run(a, R * T + i, S * T, 1);
-#pragma unroll 8
+        // sixteen loads per round: eight left a round trip per eight elements,
+        // all 32 at once (with 256 workgroups issuing) measured slower
+#pragma unroll 16
         for (int j = 0; j < T; ++j) {
           const double l = run.ld(j);
 #pragma unroll
@@ -622,7 +624,7 @@ __device__ void solve_one(const Band& a, int K, const glb_d* linv, glb_d* b, int
         const int64_t gi = R * T + i;
         const int64_t d0 = S * T - gi;   // row offset of j = 0 inside the band column
         const glb_d* col = a.ab + d0 + gi * a.ldab;
-#pragma unroll 8
+#pragma unroll 16
         for (int j = 0; j < T; ++j) {
           const int64_t dj = d0 + j;
           const double l = (S * T + j < a.n && dj <= a.k) ? col[j] : 0.0;
