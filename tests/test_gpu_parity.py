@@ -211,14 +211,16 @@ def test_walk_each_K(K):
         bc.set_walk_limit(prev)
 
 
-def test_walk_huge_ldab():
+@pytest.mark.parametrize("n,k,ldab", [(33, 32, 2900000), (130, 90, 1700000)])
+def test_walk_huge_ldab(n, k, ldab):
     """A leading dimension so large that the tile columns one step touches
     span more than 2 GB: the walk takes its per-block path (no buffer
-    resource), with the same result."""
+    resource; with K = 3 its panel and update work is split over the seven
+    waves as on the buffer path), with the same result."""
     import paper_2305_04635_amd as bc
     prev = bc.set_walk_limit(15)
     try:
-        n, k, ldab = 33, 32, 2900000
+        print("walk huge ldab", n, k, ldab, flush=True)
         l0 = synth.int_factor(n, k, 99, pow2_max=1)
         a = synth.band_ldlt(l0, k, ldab=ldab)
         l_gpu, info = gpu_factor(a, k)
