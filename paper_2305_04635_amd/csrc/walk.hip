@@ -114,16 +114,19 @@ __device__ __forceinline__ bool band_buf_fits(const Band& a, int K) {
 // (R, C) (BUF_OOB outside the band, or for every lane when !live).
 __device__ __forceinline__ void blk_offsets(const BandBuf& b, int64_t R, int64_t C, int bi, int bj, bool live,
                                             int (&off)[4]) {
+  // 32-bit arithmetic throughout: rows and columns are below 2^31 and, with
+  // band_buf_fits, every offset from column j0 is below BUF_MAX
   const int lane = lane_id();
-  const int64_t i = R * T + 16 * bi + (lane & 15);
-  const int64_t j = C * T + 16 * bj + Prec<double>::acc_col0(lane);
-  const int base = (int)((i - j) + (j - b.j0) * b.ldab);
-  const int step = Prec<double>::ACC_STEP * (int)(b.ldab - 1);
+  const int i = (int)R * T + 16 * bi + (lane & 15);
+  const int j = (int)C * T + 16 * bj + Prec<double>::acc_col0(lane);
+  const int ldab = (int)b.ldab, k = (int)b.k, n = (int)b.n;
+  const int base = (i - j) + (j - (int)b.j0) * ldab;
+  const int step = Prec<double>::ACC_STEP * (ldab - 1);
+  const bool row = live && i < n;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const int64_t d = i - j - Prec<double>::ACC_STEP * r;
-    const bool in = live && i < b.n && d >= 0 && d <= b.k;
-    off[r] = in ? (base + step * r) * (int)sizeof(double) : BUF_OOB;
+    const int d = i - j - Prec<double>::ACC_STEP * r;
+    off[r] = (row && d >= 0 && d <= k) ? (base + step * r) * (int)sizeof(double) : BUF_OOB;
   }
 }
 
