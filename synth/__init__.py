@@ -51,6 +51,8 @@ def _load():
             "synth_int_vector": (None, [I, U64, D]),
             "synth_band_symv": (None, [I, I, I, D, I, D, I, D, I]),
             "synth_batch_shapes": (None, [I, U64, I, I, I, I, P, P]),
+            "synth_int_factor_sparse": (None, [I, I, U64, F, D, I]),
+            "synth_band_llt_sparse": (None, [I, I, D, I, D, I]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -126,6 +128,21 @@ def band_ldlt(l0, k, dvec=None, ldab=None, fill=0.0):
     dkeep = None if dvec is None else np.ascontiguousarray(dvec, dtype=np.float64)
     dp = None if dkeep is None else _p(dkeep)
     _load().synth_band_ldlt(_I64(n), _I64(k), _p(l0), _I64(l0.shape[0]), dp, _p(ab), _I64(ab.shape[0]))
+    return ab
+
+
+def int_factor_sparse(n, k, seed, density):
+    """Sparse integer L0: unit diagonal, each off-diagonal +-1 with probability ``density``, else 0."""
+    l0 = empty_band(n, k)
+    _load().synth_int_factor_sparse(_I64(n), _I64(k), _U64(seed), ctypes.c_double(density), _p(l0), _I64(k + 1))
+    return l0
+
+
+def band_llt_sparse(l0, k, ldab=None, fill=0.0):
+    """A = L0 L0^T on the band, summed over each column's nonzeros (O(n m^2))."""
+    n = l0.shape[1]
+    ab = empty_band(n, k, ldab, fill)
+    _load().synth_band_llt_sparse(_I64(n), _I64(k), _p(l0), _I64(l0.shape[0]), _p(ab), _I64(ab.shape[0]))
     return ab
 
 

@@ -204,6 +204,67 @@ void synth_band_ldlt(int64_t n, int64_t k, const double *l0, int64_t ldl, const 
     }
 }
 
+/*
+ * Sparse integer-exact factor for large n and k: L0 lower band k, unit
+ * diagonal, and each off-diagonal position (j + d, j), 1 <= d <= k, holds
+ * +1 or -1 with probability `density` (else 0), drawn per position.  A =
+ * L0 L0^T is then formed from each column's list of nonzeros, A(i, j) +=
+ * L0(i, l) L0(j, l) for every pair of rows i >= j of column l, at O(n m^2)
+ * cost for m nonzeros per column instead of O(n k^2).  Every value is a small
+ * integer, so the order of the additions does not matter.  l0 and ab are
+ * zeroed on rows 0..k first (ab's other rows are left alone).
+ */
+void synth_int_factor_sparse(int64_t n, int64_t k, uint64_t seed, double density, double *l0, int64_t ldl)
+{
+    uint64_t key = make_key(seed, ST_INT + 16);
+    for (int64_t j = 0; j < n; ++j) {
+        int64_t dmax = (k < n - 1 - j) ? k : n - 1 - j;
+        l0[j * ldl] = 1.0;
+        for (int64_t d = 1; d <= k; ++d) l0[d + j * ldl] = 0.0;
+        for (int64_t d = 1; d <= dmax; ++d) {
+            uint64_t x = draw(key, (uint64_t)(j * (k + 1) + d));
+            if (u01(x) < density) l0[d + j * ldl] = (x & 1) ? 1.0 : -1.0;
+        }
+    }
+}
+
+void synth_band_llt_sparse(int64_t n, int64_t k, const double *l0, int64_t ldl, double *ab, int64_t ldab)
+{
+    /* column lists (rows ascending) and row lists (columns ascending) of the nonzeros */
+    int64_t *cptr = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    int64_t *rptr = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    for (int64_t l = 0; l < n; ++l) {
+        int64_t dmax = (k < n - 1 - l) ? k : n - 1 - l;
+        for (int64_t d = 0; d <= dmax; ++d)
+            if (l0[d + l * ldl] != 0.0) { cptr[l + 1]++; rptr[l + d + 1]++; }
+    }
+    for (int64_t i = 0; i < n; ++i) { cptr[i + 1] += cptr[i]; rptr[i + 1] += rptr[i]; }
+    int64_t nnz = cptr[n];
+    int64_t *crow = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nnz > 0 ? nnz : 1));
+    int64_t *rcol = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nnz > 0 ? nnz : 1));
+    int64_t *rfill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) rfill[i] = rptr[i];
+    for (int64_t l = 0; l < n; ++l) {
+        int64_t dmax = (k < n - 1 - l) ? k : n - 1 - l, c = cptr[l];
+        for (int64_t d = 0; d <= dmax; ++d)
+            if (l0[d + l * ldl] != 0.0) { crow[c++] = l + d; rcol[rfill[l + d]++] = l; }
+    }
+    /* column j of A: A(i, j) = sum over l in row j's list of L0(j, l) L0(i, l), i >= j */
+    #pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t j = 0; j < n; ++j) {
+        for (int64_t d = 0; d <= k; ++d) ab[d + j * ldab] = 0.0;
+        for (int64_t p = rptr[j]; p < rptr[j + 1]; ++p) {
+            int64_t l = rcol[p];
+            double vj = l0[(j - l) + l * ldl];
+            for (int64_t q = cptr[l]; q < cptr[l + 1]; ++q) {
+                int64_t i = crow[q];
+                if (i >= j) ab[(i - j) + j * ldab] += l0[(i - l) + l * ldl] * vj;
+            }
+        }
+    }
+    free(cptr); free(rptr); free(crow); free(rcol); free(rfill);
+}
+
 /* Integer right-hand-side solution x0 with entries uniform in {-8..8}. */
 void synth_int_vector(int64_t count, uint64_t seed, double *x)
 {

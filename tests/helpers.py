@@ -43,6 +43,14 @@ def rel_fro(x, ref):
     return float(np.linalg.norm(x - ref) / den) if den > 0 else float(np.linalg.norm(x))
 
 
+def col_rel_err(x, ref):
+    """Largest column error of a band array, relative to that column's norm in ``ref``
+    (an all-zero reference column counts its absolute error)."""
+    num = np.linalg.norm(x - ref, axis=0)
+    den = np.linalg.norm(ref, axis=0)
+    return float(np.max(np.where(den > 0, num / np.where(den > 0, den, 1.0), num))) if x.size else 0.0
+
+
 def dense_of(ab, k):
     """The symmetric dense matrix whose lower band is ab."""
     n = ab.shape[1]
