@@ -53,6 +53,7 @@ def _load():
             "oracle_llt_residual_rows": (None, [I, I, D, I, D, I, I, I, D]),
             "oracle_band_outer_grad": (None, [I, I, I, D, I, D, I, D, I]),
             "oracle_spbtrf": (ctypes.c_int64, [I, I, ctypes.POINTER(ctypes.c_float), I]),
+            "oracle_pbtrf_backward": (None, [I, I, D, I, D, I, D, I]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -167,6 +168,17 @@ def solve_backward(l_band, k, x, w):
     n = l_band.shape[1]
     lam = solve(l_band, k, np.asarray(w, dtype=np.float64).reshape(n, -1))
     return lam, band_outer_grad(lam, x, k, n)
+
+
+def pbtrf_backward(l_band, k, lbar_band):
+    """Reverse mode of the factorization (see band_oracle.c): the gradient with
+    respect to the stored band of A for an upstream gradient Lbar of the factor."""
+    n = l_band.shape[1]
+    lb = np.asfortranarray(lbar_band, dtype=np.float64)
+    out = np.zeros((k + 1, n), order="F")
+    _load().oracle_pbtrf_backward(n, k, _p(np.asfortranarray(l_band)), l_band.shape[0], _p(lb), lb.shape[0],
+                                  _p(out), k + 1)
+    return out
 
 
 def spbtrf(ab32, k):

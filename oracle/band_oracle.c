@@ -293,6 +293,67 @@ void oracle_band_outer_grad(int64_t n, int64_t k, int64_t nrhs, const double *la
 }
 
 /*
+ * Reverse mode of the factorization: given the factor L of A (band, LAPACK
+ * layout) and an upstream gradient Lbar = dloss/dL on the band (lower
+ * triangle), the gradient Abar = dloss/dA with respect to the stored band
+ * entries -- the entries A(i, j), i >= j, that the factorization reads.
+ *
+ * It runs the steps of Algorithm 2 (Section 3.2) backwards, in exactly the
+ * reverse of their forward order (rows i descending, within a row j
+ * descending), propagating the adjoint of each step into the adjoints of the
+ * values that step read.  Forward, entry (i, j) computes
+ *     t = sum_{l=lo}^{j-1} L(i,l) L(j,l),   lo = max(0, i-k),
+ *     L(i,i) = sqrt(A(i,i) - t)          (j = i),
+ *     L(i,j) = (A(i,j) - t) / L(j,j)     (j < i).
+ * Backwards, with W holding the accumulated adjoint of every L entry (Lbar at
+ * the start):
+ *     j = i:  Abar(i,i) = W(i,i) / (2 L(i,i)),        tbar = -Abar(i,i)
+ *     j < i:  Abar(i,j) = W(i,j) / L(j,j),            tbar = -Abar(i,j),
+ *             W(j,j) -= W(i,j) L(i,j) / L(j,j)
+ *     then for l = lo .. j-1:  W(i,l) += tbar L(j,l),  W(j,l) += tbar L(i,l)
+ * (for j = i both updates land on W(i,l), the derivative of L(i,l)^2).  When
+ * entry (i, j) is reached every later step that read L(i,j) has already been
+ * reversed, so W(i,j) is complete.  W lives in a row-band copy like the
+ * forward routine's.  Lbar and Abar are in the band layout with leading
+ * dimensions ldlb, ldab >= k+1 (they may be the same array).  L must be the
+ * factor of a positive definite A (no zero pivots).
+ */
+void oracle_pbtrf_backward(int64_t n, int64_t k, const double *l, int64_t ldl, const double *lbar,
+                           int64_t ldlb, double *abar, int64_t ldab)
+{
+    if (n <= 0) return;
+    int64_t w = k + 1;
+    double *r = to_rows(n, k, l, ldl);        /* L(i, i-k+t) */
+    double *g = to_rows(n, k, lbar, ldlb);    /* W, the adjoints */
+    double *a = (double *)calloc((size_t)n * (size_t)w, sizeof(double));
+    for (int64_t i = n - 1; i >= 0; --i) {
+        int64_t lo = i - k > 0 ? i - k : 0;
+        double *ri = r + i * w, *gi = g + i * w, *ai = a + i * w;
+        for (int64_t j = i; j >= lo; --j) {
+            double *rj = r + j * w, *gj = g + j * w;
+            double tbar;
+            if (j == i) {
+                ai[k] = gi[k] / (2.0 * ri[k]);
+                tbar = -ai[k];
+            } else {
+                double lij = ri[j - i + k], ljj = rj[k];
+                ai[j - i + k] = gi[j - i + k] / ljj;
+                tbar = -ai[j - i + k];
+                gj[k] -= gi[j - i + k] * lij / ljj;
+            }
+            for (int64_t l = lo; l < j; ++l) {
+                gi[l - i + k] += tbar * rj[l - j + k];
+                gj[l - j + k] += tbar * ri[l - i + k];
+            }
+        }
+    }
+    from_rows(n, k, a, abar, ldab);
+    free(r);
+    free(g);
+    free(a);
+}
+
+/*
  * FP32 band Cholesky: Algorithm 2 (row by row, inner bound l <= j-1) with
  * every operation in single precision (float products and sums, sqrtf,
  * float division), on a float band in the LAPACK lower layout.  Used by the
