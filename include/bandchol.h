@@ -21,7 +21,18 @@
  * device, allocated and owned by the caller.  The library never frees caller
  * memory.  It owns one workspace per device (grown on demand with hipMalloc,
  * released by bandchol_finalize); a call that needs a larger workspace than
- * the one held must therefore not run under stream capture.
+ * the one held must therefore not run under stream capture, and growing it
+ * frees the old one, which a graph captured earlier may still name: capture
+ * only after a call of the same or a larger size has run, and recapture after
+ * a larger call or after bandchol_finalize.
+ *
+ * Concurrency: the single-matrix calls (factor, solve, their _async forms, the
+ * FP32 factor, the mixed solve, the solve backward) share that workspace --
+ * ticket counters, flags and publication buffers -- and one status slot per
+ * device.  Two such calls on one device must not overlap in time, whether
+ * issued on different streams or from different threads: order them on one
+ * stream or synchronise between them.  Batch plans own their memory and do
+ * not share it.
  *
  * Streams: the synchronous calls run on the stream set with
  * bandchol_set_stream for the calling thread (default: the null stream) and
@@ -67,7 +78,9 @@ int64_t bandchol_factor(int64_t n, int64_t k, double* ab, int64_t ldab);
  *   n -1, k -2, nrhs >= 0 -3, ab (factor) -4, ldab >= k+1 -5,
  *   b device pointer, n x nrhs column-major -6, ldb >= max(1, n) -7.
  * B is overwritten by X.  The factor is not inspected for zero pivots: call
- * only after bandchol_factor returned 0.  Synchronous.
+ * only after bandchol_factor returned 0.  Synchronous.  Returns
+ * BANDCHOL_EHANG (B then unspecified) when a wait between the solve's
+ * workgroups exceeded its bound.
  */
 int64_t bandchol_solve(int64_t n, int64_t k, int64_t nrhs, const double* ab, int64_t ldab, double* b,
                        int64_t ldb);
@@ -76,6 +89,8 @@ int64_t bandchol_solve(int64_t n, int64_t k, int64_t nrhs, const double* ab, int
  * Stream-ordered forms.  No host synchronisation.  bandchol_factor_async
  * writes info (as above; 0 on success) to *d_info, a device int64.  Argument
  * codes are returned immediately.  stream is a hipStream_t (NULL = null stream).
+ * bandchol_solve_async has no status output: a wait that exceeded its bound
+ * (reported as BANDCHOL_EHANG by bandchol_solve) leaves B unspecified.
  */
 int64_t bandchol_factor_async(int64_t n, int64_t k, double* ab, int64_t ldab, int64_t* d_info,
                               void* stream);
@@ -182,7 +197,8 @@ int64_t bandchol_factor_f32(int64_t n, int64_t k, float* ab, int64_t ldab, int64
  *   ldb >= max(1,n) -7; x (device, n x nrhs, written) -8 / ldx -9; n -1, k -2,
  *   nrhs -3.  iters, fallback: host pointers or NULL.
  * Returns 0, or the info of the FP64 factor (> 0) if the fallback factor fails
- * too.  Uses internal buffers of about 12 (k+1) n + 8 n nrhs bytes.
+ * too, or BANDCHOL_EHANG (x unspecified) when a wait inside one of its band
+ * solves exceeded its bound.  Uses internal buffers of about 12 (k+1) n + 8 n nrhs bytes.
  * Synchronous on the stream of bandchol_set_stream.
  */
 int64_t bandchol_mixed_solve(int64_t n, int64_t k, int64_t nrhs, const double* ab, int64_t ldab, const double* b,
@@ -211,8 +227,10 @@ int64_t bandchol_solve_backward(int64_t n, int64_t k, int64_t nrhs, const double
 /*
  * Batches of independent systems of different orders and bandwidths.  The
  * paper's method factors one band at a time; a single band only offers the
- * parallelism of its own tile columns (Section 6 notes how little there is at
- * small bandwidths), so many independent systems are run at once: one
+ * parallelism of its own tile columns (the paper's evaluation finds its small
+ * bandwidths far from the machine's peak, Section 5, and its conclusions point
+ * at the little parallelism narrow bands offer, Section 7), so many independent
+ * systems are run at once: one
  * workgroup per system, every workgroup taking the next system from an atomic
  * counter, longest first (the estimate is (n / T) * (10 + K^2) with K the
  * number of sub-diagonal tiles).  Systems with more than 15 sub-diagonal

@@ -39,7 +39,7 @@ hipError_t bandchol_factor2_launch_f32(int64_t n, int64_t k, float* ab, int64_t 
 hipError_t bandchol_factor2_launch(int64_t n, int64_t k, double* ab, int64_t ldab, int64_t* d_info, void* ws,
                                    int grid_max, hipStream_t st);
 hipError_t bandchol_solve_launch(int64_t n, int64_t k, int64_t nrhs, const double* ab, int64_t ldab, double* b,
-                                 int64_t ldb, void* ws, int num_cus, hipStream_t st);
+                                 int64_t ldb, void* ws, int num_cus, int64_t* d_status, hipStream_t st);
 
 namespace {
 
@@ -275,7 +275,7 @@ int64_t factor_with(int64_t n, int64_t k, double* ab, int64_t ldab, int64_t* d_i
 }
 
 int64_t solve_async_impl(int64_t n, int64_t k, int64_t nrhs, const double* ab, int64_t ldab, double* b,
-                         int64_t ldb, hipStream_t st);
+                         int64_t ldb, hipStream_t st, int64_t* d_status = nullptr);
 
 int64_t solve_backward_impl(int64_t n, int64_t k, int64_t nrhs, const double* ab, int64_t ldab, const double* x,
                             int64_t ldx, double* g, int64_t ldg, double* gab, int64_t ldgab, hipStream_t st) {
@@ -302,8 +302,10 @@ int64_t solve_backward_impl(int64_t n, int64_t k, int64_t nrhs, const double* ab
   return 0;
 }
 
-int64_t solve_async_impl(int64_t n, int64_t k, int64_t nrhs, const double* ab, int64_t ldab, double* b,
-                         int64_t ldb, hipStream_t st) {
+// d_status (device int64, may be NULL): set to BANDCHOL_EHANG when a wait of
+// the solve gave up; never cleared here.
+int64_t solve_args(int64_t n, int64_t k, int64_t nrhs, const double* ab, int64_t ldab, const double* b,
+                   int64_t ldb) {
   if (n < 0) return -1;
   if (k < 0) return -2;
   if (nrhs < 0) return -3;
@@ -311,12 +313,19 @@ int64_t solve_async_impl(int64_t n, int64_t k, int64_t nrhs, const double* ab, i
   if (ldab < k + 1) return -5;
   if (b == nullptr && n > 0 && nrhs > 0) return -6;
   if (ldb < (n > 1 ? n : 1)) return -7;
+  return 0;
+}
+
+int64_t solve_async_impl(int64_t n, int64_t k, int64_t nrhs, const double* ab, int64_t ldab, double* b,
+                         int64_t ldb, hipStream_t st, int64_t* d_status) {
+  const int64_t bad = solve_args(n, k, nrhs, ab, ldab, b, ldb);
+  if (bad) return bad;
   if (n == 0 || nrhs == 0) return 0;
   const int64_t kk = k < n - 1 ? k : n - 1;
   hipError_t e;
   void* ws = workspace(bandchol_solve_workspace(n, kk), &e);
   if (!ws) { set_err("workspace", e); return BANDCHOL_EHIP; }
-  e = bandchol_solve_launch(n, kk, nrhs, ab, ldab, b, ldb, ws, num_cus(), st);
+  e = bandchol_solve_launch(n, kk, nrhs, ab, ldab, b, ldb, ws, num_cus(), d_status, st);
   if (e != hipSuccess) { set_err("solve launch", e); return BANDCHOL_EHIP; }
   return 0;
 }
@@ -401,6 +410,8 @@ int64_t mixed_solve_impl(int64_t n, int64_t k, int64_t nrhs, const double* ab, i
   // FP32 factor of fl32(A)
   e = bandchol_band_to_f32(n, kk, ab, ldab, l32, ldl, st);
   if (e != hipSuccess) return fail("mixed: convert");
+  int64_t* dstatus = dinfo + 1;   // BANDCHOL_EHANG once a solve's wait gave up
+  set_info_kernel<<<1, 1, 0, st>>>(dstatus, 0);
   int64_t rc = factor_f32_impl(n, kk, l32, ldl, dinfo, st);
   if (rc != 0) return rc;
   int64_t info32 = 0;
@@ -418,7 +429,7 @@ int64_t mixed_solve_impl(int64_t n, int64_t k, int64_t nrhs, const double* ab, i
     e = hipMemcpy2DAsync(x, sizeof(double) * ldx, b, sizeof(double) * ldb, sizeof(double) * n, nrhs,
                          hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return fail("mixed: copy");
-    rc = solve_async_impl(n, kk, nrhs, l, ldl, x, ldx, st);
+    rc = solve_async_impl(n, kk, nrhs, l, ldl, x, ldx, st, dstatus);
     if (rc != 0) return rc;
     std::vector<double> dprev(nrhs, 0.0);
     for (;;) {
@@ -431,7 +442,7 @@ int64_t mixed_solve_impl(int64_t n, int64_t k, int64_t nrhs, const double* ab, i
         if (!(from_bits(hn[c]) <= tol * from_bits(hn[nrhs + c]))) done = false;
       if (done) break;
       if (it == MIXED_ITMAX) { reason = 2; break; }
-      rc = solve_async_impl(n, kk, nrhs, l, ldl, r, n, st);
+      rc = solve_async_impl(n, kk, nrhs, l, ldl, r, n, st, dstatus);
       if (rc != 0) return rc;
       e = bandchol_colmax(n, nrhs, r, n, nrm, st);
       if (e != hipSuccess || !fetch(nrhs)) return fail("mixed: correction");
@@ -447,7 +458,19 @@ int64_t mixed_solve_impl(int64_t n, int64_t k, int64_t nrhs, const double* ab, i
   }
   if (iters) *iters = it;
   if (fallback) *fallback = reason;
-  if (reason == 0) return 0;
+  // a solve whose wait gave up left x unspecified: report it, whatever the refinement decided
+  auto solves_ok = [&]() -> int64_t {
+    int64_t status = 0;
+    e = hipMemcpyAsync(&status, dstatus, sizeof status, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail("mixed: status");
+    if (status == BANDCHOL_EHANG) {
+      snprintf(g_err, sizeof g_err, "mixed solve: a device-side wait exceeded its bound");
+      return (int64_t)BANDCHOL_EHANG;
+    }
+    return 0;
+  };
+  if (reason == 0) return solves_ok();
   // FP64 fallback: factor a copy of A into L, then solve
   e = hipMemcpy2DAsync(l, sizeof(double) * ldl, ab, sizeof(double) * ldab, sizeof(double) * ldl, n,
                        hipMemcpyDeviceToDevice, st);
@@ -462,11 +485,11 @@ int64_t mixed_solve_impl(int64_t n, int64_t k, int64_t nrhs, const double* ab, i
   e = hipMemcpy2DAsync(x, sizeof(double) * ldx, b, sizeof(double) * ldb, sizeof(double) * n, nrhs,
                        hipMemcpyDeviceToDevice, st);
   if (e != hipSuccess) return fail("mixed: copy");
-  rc = solve_async_impl(n, kk, nrhs, l, ldl, x, ldx, st);
+  rc = solve_async_impl(n, kk, nrhs, l, ldl, x, ldx, st, dstatus);
   if (rc != 0) return rc;
   e = hipStreamSynchronize(st);
   if (e != hipSuccess) return fail("mixed: fallback solve");
-  return 0;
+  return solves_ok();
 }
 
 }  // namespace
@@ -596,10 +619,23 @@ int64_t bandchol_factor(int64_t n, int64_t k, double* ab, int64_t ldab) {
 int64_t bandchol_solve(int64_t n, int64_t k, int64_t nrhs, const double* ab, int64_t ldab, double* b,
                        int64_t ldb) {
   g_err[0] = 0;
-  int64_t rc = solve_async_impl(n, k, nrhs, ab, ldab, b, ldb, g_stream);
-  if (rc != 0 || n == 0 || nrhs == 0) return rc;
-  hipError_t e = hipStreamSynchronize(g_stream);
+  const int64_t bad = solve_args(n, k, nrhs, ab, ldab, b, ldb);
+  if (bad || n == 0 || nrhs == 0) return bad;
+  hipError_t e;
+  int64_t *h = nullptr, *d_status = nullptr;
+  if (!info_slots(&h, &d_status, &e)) { set_err("info slots", e); return BANDCHOL_EHIP; }
+  set_info_kernel<<<1, 1, 0, g_stream>>>(d_status, 0);
+  e = hipGetLastError();
   if (e != hipSuccess) { set_err("solve", e); return BANDCHOL_EHIP; }
+  int64_t rc = solve_async_impl(n, k, nrhs, ab, ldab, b, ldb, g_stream, d_status);
+  if (rc != 0) return rc;
+  e = hipMemcpyAsync(h, d_status, sizeof(int64_t), hipMemcpyDeviceToHost, g_stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(g_stream);
+  if (e != hipSuccess) { set_err("solve", e); return BANDCHOL_EHIP; }
+  if (*h == BANDCHOL_EHANG) {
+    snprintf(g_err, sizeof g_err, "solve: a device-side wait exceeded its bound");
+    return BANDCHOL_EHANG;
+  }
   return 0;
 }
 
@@ -768,7 +804,7 @@ int64_t bandchol_batch_solve(bandchol_batch_t p, int64_t nrhs, void* stream) {
   for (size_t j = 0; j < p->wide.size() && e == hipSuccess; ++j) {
     const WalkSys& w = p->wide[j];
     if (w.n == 0) continue;
-    e = bandchol_solve_launch(w.n, w.k, nrhs, w.ab, w.ldab, w.b, w.ldb, p->d_wide_ws, num_cus(), st);
+    e = bandchol_solve_launch(w.n, w.k, nrhs, w.ab, w.ldab, w.b, w.ldb, p->d_wide_ws, num_cus(), nullptr, st);
   }
   if (e != hipSuccess) { set_err("batch solve", e); return BANDCHOL_EHIP; }
   return 0;
@@ -839,7 +875,7 @@ int64_t bandchol_batch_backward(bandchol_batch_t p, int64_t nrhs, void* stream) 
     const WalkSys& w = p->wide[j];
     if (w.n == 0) continue;
     e = bandchol_solve_launch(w.n, w.k, nrhs, w.ab, w.ldab, p->wide_g[j], w.n > 1 ? w.n : 1, p->d_wide_ws,
-                              num_cus(), st);
+                              num_cus(), nullptr, st);
   }
   if (e == hipSuccess) e = bandchol_outer_grad_launch(p->d_adj, (int)p->batch, p->nmax, nrhs, st);
   if (e != hipSuccess) { set_err("batch backward", e); return BANDCHOL_EHIP; }

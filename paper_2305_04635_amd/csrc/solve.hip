@@ -32,10 +32,12 @@
 // loaded two steps ahead, into two register stages used alternately, so that
 // a step costs its arithmetic and two barriers, not memory latencies.
 #include <stdint.h>
+#include <stdlib.h>
 
+#include "bandchol.h"
 #include "common.h"
 
-namespace bandchol_solve {
+namespace bandchol_sv {
 
 using namespace bandchol;
 
@@ -438,7 +440,7 @@ __global__ void __launch_bounds__(NT) solve_kernel(SolveArgs S) {
 // Fills the first len elements of the 4 publication buffers (stride apart)
 // with the unset pattern, zeroes the counters and sets the QP zeros.
 __global__ void solve_fill_kernel(glb_d* p, int64_t len, int64_t stride, unsigned* queues, glb_i* abort_flag,
-                                  glb_d* zero) {
+                                  glb_d* zero, int abort_preset) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t x = g; x < 4 * len; x += (int64_t)gridDim.x * blockDim.x)
     p[(x / len) * stride + x % len] = __longlong_as_double(UNSET);
@@ -446,8 +448,15 @@ __global__ void solve_fill_kernel(glb_d* p, int64_t len, int64_t stride, unsigne
   if (g == 0) {
     queues[0] = 0;
     queues[1] = 0;
-    *abort_flag = 0;
+    *abort_flag = abort_preset;
   }
+}
+
+// After a forward + back pair: a wait that gave up (abort flag raised) makes
+// the call's status BANDCHOL_EHANG.  The status is only ever set here, never
+// cleared: the caller clears it once per call.
+__global__ void solve_status_kernel(const glb_i* abort_flag, int64_t* status) {
+  if (*abort_flag) *status = BANDCHOL_EHANG;
 }
 
 // Per tile C, L(C,C)^{-T} (row-major): lanes 0..T-1 hold the rows of L(C,C),
@@ -578,7 +587,7 @@ inline int blocks_of_band(int64_t n, int64_t k) {
   return KS;
 }
 
-}  // namespace bandchol_solve
+}  // namespace bandchol_sv
 
 // Host side, called by the C-ABI (same library).  Workspace layout, in bytes
 // from `ws`: [0,256) two ticket counters, the abort flag, (at 64) QP zeros
@@ -588,15 +597,15 @@ inline int blocks_of_band(int64_t n, int64_t k) {
 // nrhs * NBT); then the inverted tiles, 2 * NB * T * T doubles; then the
 // operand buffer, NB * chunk_len(ST) doubles.
 size_t bandchol_solve_workspace(int64_t n, int64_t k) {
-  using namespace bandchol_solve;
+  using namespace bandchol_sv;
   const int64_t NB = (n + SB - 1) / SB, NBT = NB * SB;
   const int ST = spine_width(blocks_of_band(n, k));
   return 256 + sizeof(double) * ((size_t)4 * RHS_MAX * NBT + (size_t)2 * NB * T * T + (size_t)NB * chunk_len(ST));
 }
 
 hipError_t bandchol_solve_launch(int64_t n, int64_t k, int64_t nrhs, const double* ab, int64_t ldab, double* b,
-                                 int64_t ldb, void* ws, int num_cus, hipStream_t st) {
-  using namespace bandchol_solve;
+                                 int64_t ldb, void* ws, int num_cus, int64_t* d_status, hipStream_t st) {
+  using namespace bandchol_sv;
   const int NB = (int)((n + SB - 1) / SB);
   const int64_t NBT = (int64_t)NB * SB;
   const int KS = blocks_of_band(n, k);
@@ -614,6 +623,12 @@ hipError_t bandchol_solve_launch(int64_t n, int64_t k, int64_t nrhs, const doubl
   const int nhelp = KS > ST ? NB - ST - 1 : 0;
   // one workgroup per CU at most: the spine keeps a CU to itself
   const int grid = 1 + nhelp < num_cus ? 1 + nhelp : num_cus;
+  // Testing aid: BANDCHOL_TEST_SOLVE_ABORT=1 starts every pass with the abort
+  // flag raised, as if a wait had given up, so that the status path can be
+  // checked without making any wait actually time out (waits that find their
+  // data published never look at the flag; the others return at once).
+  const char* preset_env = getenv("BANDCHOL_TEST_SOLVE_ABORT");
+  const int preset = (preset_env && preset_env[0] == '1') ? 2 : 0;
   for (int64_t r0 = 0; r0 < nrhs; r0 += RHS_MAX) {
     const int nr = (int)(nrhs - r0 < RHS_MAX ? nrhs - r0 : RHS_MAX);
     const size_t stride = (size_t)RHS_MAX * NBT;
@@ -627,9 +642,10 @@ hipError_t bandchol_solve_launch(int64_t n, int64_t k, int64_t nrhs, const doubl
     const int64_t len = (int64_t)nr * NBT;
     const int64_t fg = (4 * len + 255) / 256;
     solve_fill_kernel<<<(unsigned)(fg < 2048 ? fg : 2048), 256, 0, st>>>(pubarea, len, (int64_t)stride, queues,
-                                                                         abort_flag, zero);
+                                                                         abort_flag, zero, preset);
     if (ST == 1) launch_pair<1>(a, dinvt, ops, F, Bk, grid, st);
     else launch_pair<ST_MAX>(a, dinvt, ops, F, Bk, grid, st);
+    if (d_status) solve_status_kernel<<<1, 1, 0, st>>>(abort_flag, d_status);
   }
   return hipGetLastError();
 }
