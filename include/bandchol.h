@@ -57,6 +57,7 @@ extern "C" {
 
 #define BANDCHOL_EHIP (-1000)
 #define BANDCHOL_EHANG (-1001)
+#define BANDCHOL_ETOOBIG (-1002)
 
 /*
  * Factor A = L L^T in place (LAPACK pbtrf, uplo = 'L').
@@ -96,6 +97,28 @@ int64_t bandchol_factor_async(int64_t n, int64_t k, double* ab, int64_t ldab, in
                               void* stream);
 int64_t bandchol_solve_async(int64_t n, int64_t k, int64_t nrhs, const double* ab, int64_t ldab,
                              double* b, int64_t ldb, void* stream);
+
+/*
+ * For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the factor of
+ * bandchol_factor_async (same arguments, same result bit for bit, same
+ * schedule) that allocates nothing.  Its working memory (ticket counter,
+ * flags, tile inverses and pre-accumulated tiles of the multi-workgroup
+ * schedule) lives in a fixed device array of 128 MiB that every GPU the
+ * library runs on holds from module load until the process ends; the call
+ * makes no hipMalloc, hipFree or other allocating call.  It needs
+ *   256 + 256 * ceil(4 (NB (K + 1) + 2 NB) / 256) + 32768 NB bytes,
+ *   NB = ceil(n / 32), K = ceil(min(k, n-1) / 32),
+ * which fits for n up to about 130000 at any k <= 2000; a larger band returns
+ * BANDCHOL_ETOOBIG (nothing launched; bandchol_last_error() gives the sizes).
+ * Every call on a GPU shares that GPU's array and leaves its contents behind
+ * (the kernels clear what must start at zero): calls that overlap in time on
+ * one GPU -- on different streams or from different threads -- race.  The
+ * first call on each device looks the array's address up (with that device
+ * current).  Argument codes and d_info as bandchol_factor_async.
+ */
+int64_t bandchol_factor_noalloc(int64_t n, int64_t k, double* ab, int64_t ldab, int64_t* d_info,
+                                void* stream);
 
 /* Stream used by the synchronous calls of the calling thread (hipStream_t). */
 int64_t bandchol_set_stream(void* stream);

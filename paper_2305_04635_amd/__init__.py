@@ -26,6 +26,7 @@ SIGNATURES = {
     "bandchol_solve": (_I64, [_I64, _I64, _I64, _VP, _I64, _VP, _I64]),
     "bandchol_factor_async": (_I64, [_I64, _I64, _VP, _I64, _VP, _VP]),
     "bandchol_solve_async": (_I64, [_I64, _I64, _I64, _VP, _I64, _VP, _I64, _VP]),
+    "bandchol_factor_noalloc": (_I64, [_I64, _I64, _VP, _I64, _VP, _VP]),
     "bandchol_set_stream": (_I64, [_VP]),
     "bandchol_last_error": (ctypes.c_char_p, []),
     "bandchol_finalize": (None, []),
@@ -49,6 +50,7 @@ SIGNATURES = {
 
 EHIP = -1000
 EHANG = -1001
+ETOOBIG = -1002
 
 
 class BandCholError(RuntimeError):
@@ -183,6 +185,18 @@ def factor_async(ab, n, k, d_info, ldab=None):
     rc = load().bandchol_factor_async(n, k, ab.data_ptr(), ldab, d_info.data_ptr(), _stream())
     if rc != 0:
         _raise(rc, "bandchol_factor_async")
+
+
+def factor_noalloc(ab, n, k, d_info, ldab=None):
+    """As ``factor_async``, through the entry point that allocates no device memory."""
+    import torch
+    ldab = k + 1 if ldab is None else ldab
+    _check_tensor(ab, "ab")
+    if d_info.dtype != torch.int64 or not d_info.is_cuda:
+        raise TypeError("d_info must be an int64 GPU tensor")
+    rc = load().bandchol_factor_noalloc(n, k, ab.data_ptr(), ldab, d_info.data_ptr(), _stream())
+    if rc != 0:
+        _raise(rc, "bandchol_factor_noalloc")
 
 
 def solve(ab, n, k, b, nrhs=None, ldab=None, ldb=None):

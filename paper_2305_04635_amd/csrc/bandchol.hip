@@ -235,9 +235,14 @@ int spine_grid(int want) {
   return grid;
 }
 
-int64_t factor_with(int64_t n, int64_t k, double* ab, int64_t ldab, int64_t* d_info, int wgs, hipStream_t st);
+int64_t factor_with(int64_t n, int64_t k, double* ab, int64_t ldab, int64_t* d_info, int wgs, hipStream_t st,
+                    void* fixed_ws = nullptr, size_t fixed_size = 0);
 
-int64_t factor_async_impl(int64_t n, int64_t k, double* ab, int64_t ldab, int64_t* d_info, hipStream_t st) {
+// fixed_ws: when not NULL, the spine's working memory is taken from this
+// buffer of fixed_size bytes instead of the library's workspace (nothing is
+// allocated); a band whose working memory exceeds it is rejected.
+int64_t factor_async_impl(int64_t n, int64_t k, double* ab, int64_t ldab, int64_t* d_info, hipStream_t st,
+                          void* fixed_ws = nullptr, size_t fixed_size = 0) {
   if (n < 0) return -1;
   if (k < 0) return -2;
   if (ab == nullptr && n > 0) return -3;
@@ -254,11 +259,12 @@ int64_t factor_async_impl(int64_t n, int64_t k, double* ab, int64_t ldab, int64_
     return 0;
   }
   const int K = tile_diagonals(n, k);
-  return factor_with(n, k, ab, ldab, d_info, schedule_wgs(n, K), st);
+  return factor_with(n, k, ab, ldab, d_info, schedule_wgs(n, K), st, fixed_ws, fixed_size);
 }
 
 // The factor with a given schedule (1 = walk, else spine workgroups).
-int64_t factor_with(int64_t n, int64_t k, double* ab, int64_t ldab, int64_t* d_info, int wgs, hipStream_t st) {
+int64_t factor_with(int64_t n, int64_t k, double* ab, int64_t ldab, int64_t* d_info, int wgs, hipStream_t st,
+                    void* fixed_ws, size_t fixed_size) {
   hipError_t e;
   const int K = tile_diagonals(n, k);
   if (wgs == 1 && K <= WALK_KMAX) {
@@ -267,8 +273,19 @@ int64_t factor_with(int64_t n, int64_t k, double* ab, int64_t ldab, int64_t* d_i
     if (e != hipSuccess) { set_err("factor launch", e); return BANDCHOL_EHIP; }
     return 0;
   }
-  void* w2 = workspace(bandchol_factor2_workspace(n, K), &e);
-  if (!w2) { set_err("workspace", e); return BANDCHOL_EHIP; }
+  const size_t need = bandchol_factor2_workspace(n, K);
+  void* w2 = nullptr;
+  if (fixed_ws) {
+    if (need > fixed_size) {
+      snprintf(g_err, sizeof g_err, "factor: n = %lld, k = %lld needs %zu bytes of working memory, more than the %zu "
+               "of the fixed scratch array", (long long)n, (long long)k, need, fixed_size);
+      return BANDCHOL_ETOOBIG;
+    }
+    w2 = fixed_ws;
+  } else {
+    w2 = workspace(need, &e);
+    if (!w2) { set_err("workspace", e); return BANDCHOL_EHIP; }
+  }
   e = bandchol_factor2_launch(n, k, ab, ldab, d_info, w2, spine_grid(wgs), st);
   if (e != hipSuccess) { set_err("factor launch", e); return BANDCHOL_EHIP; }
   return 0;
@@ -492,6 +509,40 @@ int64_t mixed_solve_impl(int64_t n, int64_t k, int64_t nrhs, const double* ab, i
   return solves_ok();
 }
 
+// ------------------------------------------- the factor that allocates nothing
+// bandchol_factor_noalloc takes the spine's working memory (ticket counter,
+// flags, tile inverses, pre-accumulated tiles) from this file-scope device
+// array instead of the workspace.  Every device the library runs on holds its
+// own copy from module load to process end.  In host code `scratch` names a
+// host-side stand-in, not device memory: the kernels receive the address that
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)128 << 20;
+__device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};   // per device: address of its `scratch`
+
+// Address of the current device's scratch array, looked up once per device
+// (with that device current) and kept.
+void* scratch_on_current_device(hipError_t* err) {
+  int dev = 0;
+  *err = hipGetDevice(&dev);
+  if (*err != hipSuccess) return nullptr;
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    *err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (*err != hipSuccess) return nullptr;
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
 }  // namespace
 
 // ----------------------------------------------------------------- batches
@@ -595,6 +646,19 @@ int64_t bandchol_solve_async(int64_t n, int64_t k, int64_t nrhs, const double* a
                              int64_t ldb, void* stream) {
   g_err[0] = 0;
   return solve_async_impl(n, k, nrhs, ab, ldab, b, ldb, (hipStream_t)stream);
+}
+
+int64_t bandchol_factor_noalloc(int64_t n, int64_t k, double* ab, int64_t ldab, int64_t* d_info, void* stream) {
+  g_err[0] = 0;
+  if (n < 0) return -1;
+  if (k < 0) return -2;
+  if (ab == nullptr && n > 0) return -3;
+  if (ldab < k + 1) return -4;
+  if (d_info == nullptr) return -5;
+  hipError_t e;
+  void* ptr = scratch_on_current_device(&e);
+  if (!ptr) { set_err("scratch address", e); return BANDCHOL_EHIP; }
+  return factor_async_impl(n, k, ab, ldab, d_info, (hipStream_t)stream, ptr, NOALLOC_SCRATCH_BYTES);
 }
 
 int64_t bandchol_factor(int64_t n, int64_t k, double* ab, int64_t ldab) {

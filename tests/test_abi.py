@@ -38,6 +38,11 @@ def test_bad_arguments_rejected_on_host():
     assert lib.bandchol_factor(5, 2, None, 3) == -3
     assert lib.bandchol_factor(5, 2, 8, 2) == -4
     assert lib.bandchol_factor_async(5, 2, 8, 3, None, None) == -5
+    assert lib.bandchol_factor_noalloc(-1, 2, None, 3, None, None) == -1
+    assert lib.bandchol_factor_noalloc(5, -1, None, 3, None, None) == -2
+    assert lib.bandchol_factor_noalloc(5, 2, None, 3, None, None) == -3
+    assert lib.bandchol_factor_noalloc(5, 2, 8, 2, None, None) == -4
+    assert lib.bandchol_factor_noalloc(5, 2, 8, 3, None, None) == -5
     assert lib.bandchol_solve(-1, 2, 1, None, 3, None, 5) == -1
     assert lib.bandchol_solve(5, -2, 1, None, 3, None, 5) == -2
     assert lib.bandchol_solve(5, 2, -1, None, 3, None, 5) == -3
