@@ -248,6 +248,29 @@ int64_t bandchol_solve_backward(int64_t n, int64_t k, int64_t nrhs, const double
                                 int64_t ldx, double* g, int64_t ldg, double* gab, int64_t ldgab, void* stream);
 
 /*
+ * Reverse mode of the factorization, for a loss that depends on the factor L
+ * of A = L L^T through an upstream gradient Lbar = dloss/dL (lower band):
+ * the gradient Abar = dloss/dA with respect to the stored band entries A(i, j),
+ * i >= j, i.e. the entries the factorization reads (a stored entry below the
+ * diagonal stands for both A(i, j) and A(j, i)).  With M = L, for the dense
+ * matrix this is Abar(i, j) = S(i, j) + S(j, i) (i > j), Abar(i, i) = S(i, i),
+ * S = L^{-T} Phi(L^T Lbar) L^{-1}, Phi = lower triangle with half the
+ * diagonal; it is computed tile by tile on the band only, reversing the
+ * potrf / trsm / gemm / syrk steps of Algorithm 1 (Section 3) in reverse
+ * order.  (The paper covers only the forward factorization.)
+ *   n -1, k -2, l = the factor from bandchol_factor (device) -3, ldl >= k+1 -4,
+ *   lbar (device, band layout, rows 0..k read) -5, ldlb >= k+1 -6,
+ *   abar (device, band layout, rows 0..k written; may be the same array as
+ *   lbar with ldab = ldlb) -7, ldab >= k+1 -8.
+ * d_status: device int64 or NULL; receives 0, or BANDCHOL_EHANG when a wait
+ * between the kernel's workgroups exceeded its bound (abar then unspecified).
+ * Stream-ordered on `stream`; uses the library's workspace (about 8 T^2 bytes
+ * per tile of n plus 16 T^2 per tile of k, T = bandchol_tile()).
+ */
+int64_t bandchol_factor_backward(int64_t n, int64_t k, const double* l, int64_t ldl, const double* lbar,
+                                 int64_t ldlb, double* abar, int64_t ldab, int64_t* d_status, void* stream);
+
+/*
  * Batches of independent systems of different orders and bandwidths.  The
  * paper's method factors one band at a time; a single band only offers the
  * parallelism of its own tile columns (the paper's evaluation finds its small

@@ -37,6 +37,7 @@ SIGNATURES = {
     "bandchol_batch_solve": (_I64, [_VP, _I64, _VP]),
     "bandchol_batch_destroy": (None, [_VP]),
     "bandchol_solve_backward": (_I64, [_I64, _I64, _I64, _VP, _I64, _VP, _I64, _VP, _I64, _VP, _I64, _VP]),
+    "bandchol_factor_backward": (_I64, [_I64, _I64, _VP, _I64, _VP, _I64, _VP, _I64, _VP, _VP]),
     "bandchol_batch_set_adjoint": (_I64, [_VP, _VP, _VP, _VP]),
     "bandchol_batch_backward": (_I64, [_VP, _I64, _VP]),
     "bandchol_factor_f32": (_I64, [_I64, _I64, _VP, _I64, _VP, _VP]),
@@ -273,6 +274,25 @@ def solve_backward(ab, n, k, x, g, gab, nrhs=None, ldab=None, ldgab=None):
         _raise(rc, "bandchol_solve_backward")
 
 
+def factor_backward(l, n, k, lbar, abar, d_status=None, ldl=None, ldlb=None, ldab=None):
+    """Reverse mode of ``factor`` (stream-ordered): ``abar`` receives the gradient with
+    respect to the stored band of A for the upstream gradient ``lbar`` of the factor ``l``
+    (all band tensors; ``abar`` may be ``lbar``).  ``d_status``: optional int64 GPU
+    tensor, set to 0 or EHANG."""
+    import torch
+    ldl = k + 1 if ldl is None else ldl
+    ldlb = k + 1 if ldlb is None else ldlb
+    ldab = k + 1 if ldab is None else ldab
+    for t, name in ((l, "l"), (lbar, "lbar"), (abar, "abar")):
+        _check_tensor(t, name)
+    if d_status is not None and (d_status.dtype != torch.int64 or not d_status.is_cuda):
+        raise TypeError("d_status must be an int64 GPU tensor")
+    rc = load().bandchol_factor_backward(n, k, l.data_ptr(), ldl, lbar.data_ptr(), ldlb, abar.data_ptr(), ldab,
+                                         None if d_status is None else d_status.data_ptr(), _stream())
+    if rc != 0:
+        _raise(rc, "bandchol_factor_backward")
+
+
 class BatchPlan:
     """Batch of independent band systems (``bandchol_batch_*``).
 
@@ -364,40 +384,74 @@ class BatchPlan:
 def _autograd_functions():
     import torch
 
+    def refactor(ab, k):
+        """A fresh factor of the band ``ab`` (the recompute path of the backward passes)."""
+        l = ab.detach().contiguous().clone()
+        info = factor(l, l.shape[0], k)
+        if info != 0:
+            raise BandCholError("matrix is not positive definite (info = %d)" % info)
+        return l
+
     class BandSolve(torch.autograd.Function):
         """x = A^{-1} b with A given by its lower band ``ab`` of shape (n, k+1)
         (row j = band column j) and b of shape (n,) or (n, nrhs).  Backward:
-        db = A^{-1} dx, dab = band gradient (see bandchol_solve_backward)."""
+        db = A^{-1} dx, dab = band gradient (see bandchol_solve_backward).
+        recompute=True keeps no factor between the passes: backward factors
+        A again (the band ``ab`` is held anyway), trading one factorization for
+        a band-sized buffer per system."""
 
         @staticmethod
-        def forward(ctx, ab, b, k):
+        def forward(ctx, ab, b, k, recompute=False):
             n = ab.shape[0]
-            l = ab.detach().contiguous().clone()
-            info = factor(l, n, k)
-            if info != 0:
-                raise BandCholError("matrix is not positive definite (info = %d)" % info)
+            l = refactor(ab, k)
             xb = b.detach().t().contiguous() if b.dim() == 2 else b.detach().contiguous().clone()
             nrhs = b.shape[1] if b.dim() == 2 else 1
             solve_async(l, n, k, xb, nrhs=nrhs)
-            ctx.k, ctx.nrhs, ctx.two_d = k, nrhs, b.dim() == 2
-            ctx.save_for_backward(l, xb)
+            ctx.k, ctx.nrhs, ctx.two_d, ctx.recompute = k, nrhs, b.dim() == 2, recompute
+            ctx.save_for_backward(ab if recompute else l, xb)
             return xb.t() if b.dim() == 2 else xb
 
         @staticmethod
         def backward(ctx, gx):
-            l, xb = ctx.saved_tensors
-            n, k = l.shape[0], ctx.k
+            saved, xb = ctx.saved_tensors
+            k = ctx.k
+            l = refactor(saved, k) if ctx.recompute else saved
+            n = l.shape[0]
             g = gx.t().contiguous() if ctx.two_d else gx.contiguous().clone()
             gab = torch.zeros_like(l)
             solve_backward(l, n, k, xb, g, gab, nrhs=ctx.nrhs)
-            return gab, (g.t() if ctx.two_d else g), None
+            return gab, (g.t() if ctx.two_d else g), None, None
+
+    class BandCholesky(torch.autograd.Function):
+        """L = chol(A) on the band: ``ab`` of shape (n, k+1) (row j = band column j)
+        -> the factor in the same layout.  Backward: the reverse mode of the
+        factorization (bandchol_factor_backward), gradient on the stored band."""
+
+        @staticmethod
+        def forward(ctx, ab, k):
+            l = refactor(ab, k)
+            ctx.k = k
+            ctx.save_for_backward(l)
+            return l
+
+        @staticmethod
+        def backward(ctx, gl):
+            (l,) = ctx.saved_tensors
+            n, k = l.shape[0], ctx.k
+            gab = gl.detach().contiguous().clone()
+            # the band's bottom-right corner (past row n-1) holds no entry
+            status = torch.zeros(1, dtype=torch.int64, device=l.device)
+            factor_backward(l, n, k, gab, gab, d_status=status)
+            if int(status.item()) != 0:
+                raise BandCholError("bandchol_factor_backward: a device-side wait exceeded its bound")
+            return gab, None
 
     class BandSolveBatch(torch.autograd.Function):
         """Batch of equal-shape systems: ab (B, n, k+1), b (B, n, nrhs) -> x (B, n, nrhs),
         through one BatchPlan (factor, solve and reverse mode batched)."""
 
         @staticmethod
-        def forward(ctx, ab, b, k):
+        def forward(ctx, ab, b, k, recompute=False):
             bsz, n = ab.shape[0], ab.shape[1]
             nrhs = b.shape[2]
             l = ab.detach().contiguous().clone()
@@ -410,42 +464,69 @@ def _autograd_functions():
             if bad:
                 plan.close()
                 raise BandCholError("systems %s are not positive definite" % bad)
-            ctx.plan, ctx.nrhs = plan, nrhs
-            ctx.save_for_backward(l, xb)
+            ctx.nrhs, ctx.k, ctx.recompute = nrhs, k, recompute
+            if recompute:
+                # no factors kept: the plan (which names them) goes too
+                torch.cuda.current_stream().synchronize()
+                plan.close()
+                ctx.plan = None
+                ctx.save_for_backward(ab, xb)
+            else:
+                ctx.plan = plan
+                ctx.save_for_backward(l, xb)
             return xb.transpose(1, 2)
 
         @staticmethod
         def backward(ctx, gx):
-            l, xb = ctx.saved_tensors
+            saved, xb = ctx.saved_tensors
+            plan = ctx.plan
+            if ctx.recompute:
+                bsz, n = saved.shape[0], saved.shape[1]
+                l = saved.detach().contiguous().clone()
+                plan = BatchPlan([n] * bsz, [ctx.k] * bsz, [l[i] for i in range(bsz)], [xb[i] for i in range(bsz)])
+                info = torch.zeros(bsz, dtype=torch.int64, device=saved.device)
+                plan.factor(info)
+                if torch.count_nonzero(info).item():
+                    plan.close()
+                    raise BandCholError("refactorization failed")
+            else:
+                l = saved
             g = gx.transpose(1, 2).contiguous()
             gab = torch.zeros_like(l)
-            plan = ctx.plan
             plan.set_adjoint([g[i] for i in range(g.shape[0])], [gab[i] for i in range(gab.shape[0])])
             plan.backward(ctx.nrhs)
             torch.cuda.current_stream().synchronize()
             plan.close()
-            return gab, g.transpose(1, 2), None
+            return gab, g.transpose(1, 2), None, None
 
-    return BandSolve, BandSolveBatch
+    return BandSolve, BandSolveBatch, BandCholesky
 
 
 _FUNCS = None
 
 
-def band_solve(ab, b, k):
+def band_solve(ab, b, k, recompute=False):
     """Differentiable x = A^{-1} b (see BandSolve)."""
     global _FUNCS
     if _FUNCS is None:
         _FUNCS = _autograd_functions()
-    return _FUNCS[0].apply(ab, b, k)
+    return _FUNCS[0].apply(ab, b, k, recompute)
 
 
-def band_solve_batch(ab, b, k):
+def band_solve_batch(ab, b, k, recompute=False):
     """Differentiable batched x = A^{-1} b (see BandSolveBatch)."""
     global _FUNCS
     if _FUNCS is None:
         _FUNCS = _autograd_functions()
-    return _FUNCS[1].apply(ab, b, k)
+    return _FUNCS[1].apply(ab, b, k, recompute)
+
+
+def band_cholesky(ab, k):
+    """Differentiable band Cholesky factor L of A (see BandCholesky)."""
+    global _FUNCS
+    if _FUNCS is None:
+        _FUNCS = _autograd_functions()
+    return _FUNCS[2].apply(ab, k)
 
 
 def finalize():

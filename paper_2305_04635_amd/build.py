@@ -6,7 +6,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libbandchol.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("bandchol.hip", "walk.hip", "factor2.hip", "solve.hip", "adjoint.hip", "mixed.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("bandchol.hip", "walk.hip", "factor2.hip", "solve.hip", "adjoint.hip", "mixed.hip",
+                                                             "factor_bwd.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are switched off for all device code.

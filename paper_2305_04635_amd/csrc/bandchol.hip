@@ -28,6 +28,7 @@
 
 #include "adjoint.h"
 #include "common.h"
+#include "factor_bwd.h"
 #include "mixed.h"
 #include "walk.h"
 
@@ -743,6 +744,43 @@ int64_t bandchol_solve_backward(int64_t n, int64_t k, int64_t nrhs, const double
                                 int64_t ldx, double* g, int64_t ldg, double* gab, int64_t ldgab, void* stream) {
   g_err[0] = 0;
   return solve_backward_impl(n, k, nrhs, ab, ldab, x, ldx, g, ldg, gab, ldgab, (hipStream_t)stream);
+}
+
+int64_t bandchol_factor_backward(int64_t n, int64_t k, const double* l, int64_t ldl, const double* lbar, int64_t ldlb,
+                                 double* abar, int64_t ldab, int64_t* d_status, void* stream) {
+  g_err[0] = 0;
+  if (n < 0) return -1;
+  if (k < 0) return -2;
+  if (l == nullptr && n > 0) return -3;
+  if (ldl < k + 1) return -4;
+  if (lbar == nullptr && n > 0) return -5;
+  if (ldlb < k + 1) return -6;
+  if (abar == nullptr && n > 0) return -7;
+  if (ldab < k + 1) return -8;
+  if (n > ((int64_t)1 << 31) - T) {
+    snprintf(g_err, sizeof g_err, "n too large");
+    return -1;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e;
+  if (n == 0) {
+    if (d_status) {
+      set_info_kernel<<<1, 1, 0, st>>>(d_status, 0);
+      e = hipGetLastError();
+      if (e != hipSuccess) { set_err("factor backward", e); return BANDCHOL_EHIP; }
+    }
+    return 0;
+  }
+  const int64_t kk = k < n - 1 ? k : n - 1;
+  const int K = tile_diagonals(n, k);
+  void* ws = workspace(bandchol_fb_workspace(n, K), &e);
+  if (!ws) { set_err("workspace", e); return BANDCHOL_EHIP; }
+  bandchol_fb::FbSys s{};
+  s.l = l, s.ldl = ldl, s.lbar = lbar, s.ldlb = ldlb, s.abar = abar, s.ldab = ldab;
+  s.n = n, s.k = kk, s.K = K;
+  e = bandchol_fb_launch(s, ws, num_cus(), d_status, st);
+  if (e != hipSuccess) { set_err("factor backward launch", e); return BANDCHOL_EHIP; }
+  return 0;
 }
 
 int64_t bandchol_batch_create(int64_t batch, const int64_t* n, const int64_t* k, double* const* ab,
