@@ -9,7 +9,13 @@ N(0,1)/sqrt(k)), n = 100000, and are resident in HBM before timing starts.
 
 value = sum_k [n(k^2+3k) + 4 n k nrhs] / (wall time of one step): factor and
 solve flops over the whole step, restores included.  The factor rate per k is
-reported separately from HIP events on the launch stream.
+reported separately from HIP events on the launch stream, with its model bound
+(HBM below the ridge k ~ 156, FP64 above), the fraction of that bound, and the
+fraction of the pivot chain's floor (n times the chain step's latency, measured
+on the device by bandchol_pivot_chain_ns).  After the timed region: the
+backward error of L on sampled rows and the solve residual per k (rel_err), and
+the reverse-mode workload below as fwd_bwd (forward + backward milliseconds with
+the factor kept and recomputed, gradient errors against the oracle).
 
 --workload batched: 512 independent systems, n ~ U{1000..20000}, k ~ U{32..256}
 (diagonally dominant recipe), nrhs = 4, factored and solved by one plan whose
@@ -41,10 +47,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (vector = matrix)
-# the pivot chain's floor: one wave sweeps a 32-column diagonal tile in about 9160
-# cycles (measured on gfx950 with s_memtime, tile in isolation), at 2.4 GHz
-SWEEP_TILE_S = 9160 / 2.4e9
 PEAK_HBM_GBS = 8000.0
+RIDGE = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)   # flop/B where the two roofs meet
 DEFAULT_KS = (50, 100, 250, 500, 1000, 2000)
 
 
@@ -57,9 +61,9 @@ def solve_flops(n, k, nrhs):
     return 4 * n * k * nrhs
 
 
-# sources of the dominant kernel (the multi-workgroup spine/helper factor) and of
-# the host runtime that chooses its launch (workgroups per matrix)
-KERNEL_SOURCES = ("factor2.hip", "common.h", "bandchol.hip")
+# sources of the dominant kernel (the multi-workgroup spine/helper factor); its launch
+# shape per k (workgroups) is recorded beside the counters and compared separately
+KERNEL_SOURCES = ("factor2.hip", "common.h")
 
 
 def source_hash():
@@ -69,25 +73,57 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(ks, n_sample, seed0):
-    """The oracle (plain FP64 CPU, one thread) on the first n_sample rows of each matrix."""
+def host_cpu():
+    """(CPU model, logical CPUs, OpenMP threads the oracle's parallel loops use)."""
+    import ctypes
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        omp = int(ctypes.CDLL("libgomp.so.1").omp_get_max_threads())
+    except OSError:
+        omp = os.cpu_count() or 1
+    return model, os.cpu_count() or 1, omp
+
+
+def factor_ks_oracle(ks, n_sample, seed0, columns):
     import oracle
     import synth
     tot_flops, tot_t = 0.0, 0.0
     for k in ks:
         ab, _ = synth.band_ipm(n_sample, k, seed0 + k)
         t0 = time.perf_counter()
-        info = oracle.pbtrf(ab, k)
+        info = oracle.pbtrf(ab, k, columns=columns)
         tot_t += time.perf_counter() - t0
         assert info == 0, info
         tot_flops += factor_flops(n_sample, k)
+    return tot_flops, tot_t
+
+
+def cpu_baseline(ks, n_sample, seed0):
+    """The oracle (plain FP64 CPU) on the first n_sample rows of each matrix of the sweep:
+    its column-order form (bitwise equal to Algorithm 2 row by row) on all host threads,
+    and the row-by-row form on one thread."""
+    model, nproc, omp = host_cpu()
+    f_all, t_all = factor_ks_oracle(ks, n_sample, seed0, columns=True)
+    f_one, t_one = factor_ks_oracle(ks, n_sample, seed0, columns=False)
     return {
-        "value": round(tot_flops / tot_t / 1e9, 4),
+        "value": round(f_all / t_all / 1e9, 4),
         "unit": "GFLOP/s",
-        "cores": 1,
+        "cores": omp,
         "kind": "oracle",
         "sample": "factor only, the first %d rows of each matrix of the sweep k=%s (same recipe), "
-                  "%.1f s of CPU time" % (n_sample, ",".join(map(str, ks)), tot_t),
+                  "column-order oracle on %d OpenMP threads (its columns run on one thread below k = 64), "
+                  "%.1f s" % (n_sample, ",".join(map(str, ks)), omp, t_all),
+        "cpu_model": model,
+        "nproc": nproc,
+        "one_core": {"value": round(f_one / t_one / 1e9, 4), "unit": "GFLOP/s", "cores": 1,
+                     "sample": "same rows, row-by-row oracle (Algorithm 2), %.1f s" % t_one},
     }
 
 
@@ -102,7 +138,9 @@ def source_hash_of(files):
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(kernel_hash, name="factor_traffic.json"):
+def traffic_from_profile(kernel_hash, name="factor_traffic.json", workgroups=None, key="hbm_bytes_per_launch"):
+    """HBM bytes per launch from the committed counter summary, if it was taken from the
+    current kernel source (and, when given, the same workgroups per launch); else None."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
@@ -112,7 +150,9 @@ def traffic_from_profile(kernel_hash, name="factor_traffic.json"):
         return None
     if d.get("source_hash") != kernel_hash:
         return None
-    return d.get("hbm_bytes_per_launch")
+    if workgroups is not None and d.get("workgroups") != workgroups:
+        return None
+    return d.get(key)
 
 
 def main():
@@ -126,7 +166,8 @@ def main():
     ap.add_argument("--seed", type=int, default=1000)
     ap.add_argument("--cpu-rows", type=int, default=10000, help="rows per matrix for the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--check", action="store_true", help="sampled backward-error check after timing")
+    ap.add_argument("--no-check", action="store_true", help="skip the accuracy checks after timing")
+    ap.add_argument("--no-fwd-bwd", action="store_true", help="skip the forward+backward (reverse-mode) leg")
     ap.add_argument("--workload", choices=("sweep", "batched", "adjoint", "mixed"), default="sweep")
     ap.add_argument("--batch", type=int, default=512)
     args = ap.parse_args()
@@ -163,7 +204,8 @@ def main():
         pristine = torch.from_numpy(ab.ravel(order="F")).to(dev)
         b0 = torch.from_numpy(b.ravel(order="F")).to(dev)
         mats.append(dict(k=k, ab0=pristine, ab=torch.empty_like(pristine), b0=b0, b=torch.empty_like(b0),
-                         info=torch.zeros(1, dtype=torch.int64, device=dev), host_ab=ab if args.check else None))
+                         info=torch.zeros(1, dtype=torch.int64, device=dev),
+                         host_ab=None if args.no_check else ab, host_b=b))
         del ab
     t_gen = time.perf_counter() - t_gen
     torch.cuda.synchronize()
@@ -220,17 +262,26 @@ def main():
     del scrub
 
     ms_step = (t1 - t0) * 1e3 / args.steps
+    pivot_ns = bc.pivot_chain_ns(1 << 20)
     per_k = []
     for i, m in enumerate(mats):
         f_ms = float(np.median([evs[s][i][0].elapsed_time(evs[s][i][1]) for s in range(args.steps)]))
         s_ms = float(np.median([evs[s][i][1].elapsed_time(evs[s][i][2]) for s in range(args.steps)]))
         ff = factor_flops(n, m["k"])
+        fb = 16.0 * n * (m["k"] + 1)
+        t_fp64 = ff / (PEAK_FP64_TFLOPS * 1e12)
+        t_hbm = fb / (PEAK_HBM_GBS * 1e9)
+        bound = "hbm" if ff / fb < RIDGE else "fp64"
+        chain_ms = n * pivot_ns * 1e-6
         per_k.append({"k": m["k"], "workgroups": bc.schedule(n, m["k"]), "factor_ms": round(f_ms, 4),
                       "solve_ms": round(s_ms, 4),
                       "factor_gflops": round(ff / (f_ms * 1e-3) / 1e9, 2),
-                      "factor_frac_fp64_peak": round(ff / (f_ms * 1e-3) / (PEAK_FP64_TFLOPS * 1e12), 5),
-                      "factor_frac_hbm": round(16.0 * n * (m["k"] + 1) / (f_ms * 1e-3) / (PEAK_HBM_GBS * 1e9), 5),
-                      "factor_frac_chain": round(((n + 31) // 32) * SWEEP_TILE_S / (f_ms * 1e-3), 4),
+                      "bound": bound,
+                      "frac": round((t_hbm if bound == "hbm" else t_fp64) / (f_ms * 1e-3), 5),
+                      "factor_frac_fp64_peak": round(t_fp64 / (f_ms * 1e-3), 5),
+                      "factor_frac_hbm": round(t_hbm / (f_ms * 1e-3), 5),
+                      "chain_floor_ms": round(chain_ms, 4),
+                      "factor_frac_chain": round(chain_ms / f_ms, 4),
                       "factor_ms_cold": round(cold_ms[i], 4)})
 
     step_flops = sum(factor_flops(n, k) + solve_flops(n, k, nrhs) for k in ks)
@@ -240,32 +291,62 @@ def main():
     # spans more tile diagonals than the single-workgroup walk takes.  achieved = average
     # algorithmic flops n(k^2+3k) per launch / average launch time (HIP events on the launch
     # stream around the factor call: its two tiny set-up/finish kernels are included).
+    # The roofline object covers the launches of the dominant kernel whose model bound is
+    # the FP64 peak (k above the ridge); the HBM-bound launches (k = 50, 100) are reported
+    # beside it against 8 TB/s.  Per launch: algorithmic flops n(k^2+3k) (bytes 16 n (k+1))
+    # over the launch time from HIP events on the launch stream (the factor call's two tiny
+    # set-up/finish kernels included).
     walk_kmax = bc.set_walk_limit(-1)
     tile = bc.tile()
     spine = [i for i, m in enumerate(mats) if -(-min(m["k"], n - 1) // tile) > walk_kmax]
-    sp_ms = [float(np.mean([evs[s][i][0].elapsed_time(evs[s][i][1]) for s in range(args.steps)])) for i in spine]
-    sp_flops = [factor_flops(n, mats[i]["k"]) for i in spine]
+    mean_ms = {i: float(np.mean([evs[s][i][0].elapsed_time(evs[s][i][1]) for s in range(args.steps)]))
+               for i in spine}
+    fp64_l = [i for i in spine if per_k[i]["bound"] == "fp64"]
+    hbm_l = [i for i in spine if per_k[i]["bound"] == "hbm"]
     roofline = None
-    if spine:
-        nl = len(spine)
-        achieved = (sum(sp_flops) / nl) / (sum(sp_ms) / nl * 1e-3) / 1e12
+    if fp64_l:
+        nl = len(fp64_l)
+        avg_ms = sum(mean_ms[i] for i in fp64_l) / nl
+        avg_fl = sum(factor_flops(n, mats[i]["k"]) for i in fp64_l) / nl
+        achieved = avg_fl / (avg_ms * 1e-3) / 1e12
+        wgs = {str(mats[i]["k"]): per_k[i]["workgroups"] for i in fp64_l}
         roofline = {"bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(achieved / PEAK_FP64_TFLOPS, 5), "traffic": traffic_from_profile(source_hash()),
-                    "kernel": "factor2_kernel", "ks": [mats[i]["k"] for i in spine],
-                    "avg_launch_ms": round(sum(sp_ms) / nl, 4), "avg_flops_per_launch": sum(sp_flops) / nl}
+                    "frac": round(achieved / PEAK_FP64_TFLOPS, 5),
+                    "traffic": traffic_from_profile(source_hash(), workgroups=wgs, key="hbm_bytes_per_fp64_launch"),
+                    "kernel": "factor2_kernel", "ks": [mats[i]["k"] for i in fp64_l],
+                    "avg_launch_ms": round(avg_ms, 4), "avg_flops_per_launch": avg_fl}
+        if hbm_l:
+            hl = len(hbm_l)
+            h_ms = sum(mean_ms[i] for i in hbm_l) / hl
+            h_b = sum(16.0 * n * (mats[i]["k"] + 1) for i in hbm_l) / hl
+            roofline["hbm_bound_launches"] = {
+                "bound": "hbm", "ks": [mats[i]["k"] for i in hbm_l], "avg_launch_ms": round(h_ms, 4),
+                "achieved": round(h_b / (h_ms * 1e-3) / 1e9, 3), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(h_b / (h_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 6), "avg_bytes_per_launch": h_b}
 
-    check = None
-    if args.check:
+    accuracy = None
+    if not args.no_check:
         import oracle
-        worst = 0.0
-        for m in mats:
+        # the last timed step left L and x in the working buffers
+        for i, m in enumerate(mats):
+            k = m["k"]
             l = m["ab"].cpu().numpy().reshape(m["host_ab"].shape, order="F")
-            rows = [(r, r + 64) for r in (0, n // 2, n - 64)]
-            worst = max(worst, oracle.llt_residual(l, m["host_ab"], m["k"], rows=rows))
-        check = {"sampled_backward_error_max": worst}
+            x = m["b"].cpu().numpy().reshape(m["host_b"].shape, order="F")
+            rows = [(r, r + 64) for r in np.linspace(0, n - 64, 8).astype(int)]
+            per_k[i]["eta_F_sampled"] = oracle.llt_residual(l, m["host_ab"], k, rows=rows)
+            per_k[i]["eta_x"] = oracle.solve_residual(m["host_ab"], k, x, m["host_b"])
+        accuracy = {"eta_F_sampled_max": max(p["eta_F_sampled"] for p in per_k),
+                    "eta_x_max": max(p["eta_x"] for p in per_k),
+                    "eta_F_rows": "8 windows of 64 rows spread over the band, every k",
+                    "gate": 1e-12}
+    for m in mats:
+        m["host_ab"] = m["host_b"] = None
+    fwd_bwd = None if args.no_fwd_bwd else fwd_bwd_leg(args.seed, args.warmup, max(3, args.steps // 2),
+                                                        not args.no_check)
 
     line = {
-        "metric": "band Cholesky GFLOP/s n=1e5,k=50-2000 (FP64 factor+solve, one sweep per step)",
+        "metric": "band Cholesky GFLOP/s n=1e5,k=50-2000 (FP64 factor+solve, one sweep per step); "
+                  "fwd+bwd ms in fwd_bwd; rel err in rel_err",
         "value": round(value, 3),
         "unit": "GFLOP/s",
         "n_gpus": 1,
@@ -281,11 +362,14 @@ def main():
                                "SPD band (A = L0 L0^T + 1e-8||A|| I), LAPACK lower band ldab=k+1"
                                % (n, ",".join(map(str, ks)), nrhs),
                    "n": n, "ks": ks, "nrhs": nrhs, "tile": bc.tile(), "per_k": per_k,
+                   "pivot_chain_ns": round(pivot_ns, 3),
                    "input_generation_s": round(t_gen, 2)},
         "roofline": roofline,
     }
-    if check is not None:
-        line["check"] = check
+    if accuracy is not None:
+        line["rel_err"] = accuracy
+    if fwd_bwd is not None:
+        line["fwd_bwd"] = fwd_bwd
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(ks, args.cpu_rows, args.seed)
     print(json.dumps(line))
@@ -375,7 +459,7 @@ def bench_batched(args):
         print("bench.py: batched factorization failed: %s" % [x for x in infos if x], file=sys.stderr)
         sys.exit(1)
     check = None
-    if args.check:
+    if not args.no_check:
         import oracle
         worst = 0.0
         for i in range(0, len(ns), max(1, len(ns) // 16)):
@@ -423,6 +507,114 @@ def bench_batched(args):
         line["cpu_baseline"] = cpu_baseline_batched(ns, ks, nrhs, args.seed)
     plan.close()
     print(json.dumps(line))
+
+
+def adjoint_setup(seed, bsz=64, n=20000, k=200, nrhs=1):
+    """The reverse-mode workload: bsz diagonally dominant systems (n, k), b and w ~ N(0,1),
+    pristine copies resident on the device, and a plan for the factor, solve and reverse mode."""
+    import torch
+
+    import synth
+    import paper_2305_04635_amd as bc
+    dev = torch.device("cuda:0")
+    ab0, b0, w0 = [], [], []
+    for i in range(bsz):
+        ab0.append(torch.from_numpy(synth.band_diagdom(n, k, seed + i).ravel(order="F")).to(dev))
+        b0.append(torch.from_numpy(synth.rhs(n, nrhs, seed + i).ravel(order="F")).to(dev))
+        w0.append(torch.from_numpy(synth.normal(n * nrhs, seed + i, 1)).to(dev))
+    st = dict(bsz=bsz, n=n, k=k, nrhs=nrhs, ab0=ab0, b0=b0, w0=w0)
+    st["ab"] = [torch.empty_like(t) for t in ab0]
+    st["b"] = [torch.empty_like(t) for t in b0]
+    st["g"] = [torch.empty_like(t) for t in w0]
+    st["gab"] = [torch.zeros_like(t) for t in ab0]
+    st["plan"] = bc.BatchPlan([n] * bsz, [k] * bsz, st["ab"], st["b"])
+    st["plan"].set_adjoint(st["g"], st["gab"])
+    st["info"] = torch.zeros(bsz, dtype=torch.int64, device=dev)
+    return st
+
+
+def adjoint_replay_ms(st, warmup, steps, recompute):
+    """Median milliseconds of one graph replay of forward (factor + solve) and backward
+    (reverse mode), restores outside the timed region.  recompute: the backward factors A
+    again from the pristine band first instead of using the factor of the forward pass."""
+    import numpy as np
+    import torch
+
+    plan, nrhs = st["plan"], st["nrhs"]
+
+    def restore():
+        torch._foreach_copy_(st["ab"], st["ab0"])
+        torch._foreach_copy_(st["b"], st["b0"])
+        torch._foreach_copy_(st["g"], st["w0"])
+
+    def run():
+        plan.factor(st["info"])
+        plan.solve(nrhs)
+        if recompute:
+            torch._foreach_copy_(st["ab"], st["ab0"])
+            plan.factor(st["info"])
+        plan.backward(nrhs)
+
+    restore()
+    run()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        run()
+    times = []
+    for s in range(warmup + steps):
+        restore()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        if s >= warmup:
+            times.append(e0.elapsed_time(e1))
+    if any(int(x) != 0 for x in st["info"].cpu().tolist()):
+        print("bench.py: reverse-mode workload: factorization failed", file=sys.stderr)
+        sys.exit(1)
+    return float(np.median(times))
+
+
+def adjoint_errors(st, seed, systems=(0, 37)):
+    """db and band-gradient relative errors of the given systems against the oracle."""
+    import numpy as np
+
+    import oracle
+    import synth
+    n, k, nrhs = st["n"], st["k"], st["nrhs"]
+    e_db, e_da = 0.0, 0.0
+    for i in systems:
+        ab = synth.band_diagdom(n, k, seed + i)
+        b = synth.rhs(n, nrhs, seed + i).reshape(n, nrhs)
+        w = synth.normal(n * nrhs, seed + i, 1).reshape(n, nrhs, order="F")
+        l_or, _ = oracle.factor(ab, k)
+        x_or = oracle.solve(l_or, k, b)
+        db_or, gab_or = oracle.solve_backward(l_or, k, x_or, w)
+        db = st["g"][i].cpu().numpy().reshape(n, nrhs, order="F")
+        gab = st["gab"][i].cpu().numpy().reshape(k + 1, n, order="F")
+        e_db = max(e_db, float(np.linalg.norm(db - db_or) / np.linalg.norm(db_or)))
+        e_da = max(e_da, float(np.linalg.norm(gab - gab_or) / np.linalg.norm(gab_or)))
+    return e_db, e_da
+
+
+def fwd_bwd_leg(seed, warmup, steps, check):
+    """The reverse-mode workload inside the default run: 64 systems, n = 20000, k = 200,
+    loss = sum(w .* x); forward + backward milliseconds with the factor kept and recomputed."""
+    st = adjoint_setup(seed)
+    ms_keep = adjoint_replay_ms(st, warmup, steps, recompute=False)
+    out = {"workload": "x = A^{-1} b and the gradient of sum(w .* x) in b and the band of A, 64 diagonally "
+                       "dominant systems, n=20000, k=200, nrhs=1, one HIP graph replay",
+           "ms": round(ms_keep, 4)}
+    if check:
+        e_db, e_da = adjoint_errors(st, seed)
+        out["db_rel_err_vs_oracle"] = e_db
+        out["dA_rel_err_vs_oracle"] = e_da
+        out["checked_systems"] = [0, 37]
+    out["ms_recompute"] = round(adjoint_replay_ms(st, warmup, steps, recompute=True), 4)
+    st["plan"].close()
+    return out
 
 
 def bench_adjoint(args):
@@ -481,7 +673,7 @@ def bench_adjoint(args):
         print("bench.py: adjoint workload: factorization failed", file=sys.stderr)
         sys.exit(1)
     check = None
-    if args.check:
+    if not args.no_check:
         import oracle
         ab = synth.band_diagdom(n, k, args.seed)
         b = synth.rhs(n, nrhs, args.seed).reshape(n, nrhs)

@@ -144,6 +144,19 @@ int64_t bandchol_tile(void);
 int64_t bandchol_set_walk_limit(int64_t kmax);
 
 /*
+ * Latency of one step of the factor's pivot chain on the current device, in
+ * nanoseconds: one wave runs `steps` dependent steps of the reciprocal of a
+ * pivot (hardware estimate refined by two Newton steps, as the factor takes
+ * it) followed by the fused multiply-add that forms the next pivot, timed by
+ * the GPU's 100 MHz real-time counter.  A single band's factorization has n
+ * such steps one after another, so n times this is a floor for its time at
+ * any bandwidth.  1 <= steps <= 2^32 (-1), ns_per_step a host pointer (-2).
+ * Synchronous on the stream of bandchol_set_stream; allocates 256 bytes of
+ * device memory for the call.
+ */
+int64_t bandchol_pivot_chain_ns(int64_t steps, double* ns_per_step);
+
+/*
  * Schedule per (n, k) bucket.  The paper picks the dimension of its block
  * grid per problem with a heuristic (block size near 50, no more blocks than
  * cores) and lets users who know their bandwidths and hardware tune it

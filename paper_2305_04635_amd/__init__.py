@@ -47,6 +47,7 @@ SIGNATURES = {
     "bandchol_tune_entries": (_I64, [_I64, _VP, _VP, _VP, _VP]),
     "bandchol_tune_clear": (None, []),
     "bandchol_tune_factor": (_I64, [_I64, _I64, _I64, _VP, _VP]),
+    "bandchol_pivot_chain_ns": (_I64, [_I64, _VP]),
 }
 
 EHIP = -1000
@@ -145,6 +146,17 @@ def tune_factor(n, k, reps=3):
     if rc != 0:
         _raise(rc, "bandchol_tune_factor")
     return int(w.value), float(ms.value)
+
+
+def pivot_chain_ns(steps=1 << 20):
+    """Measured latency (ns) of one step of the factor's pivot chain on the current device."""
+    lib = load()
+    lib.bandchol_set_stream(_stream())
+    v = ctypes.c_double(0.0)
+    rc = int(lib.bandchol_pivot_chain_ns(int(steps), ctypes.byref(v)))
+    if rc != 0:
+        _raise(rc, "bandchol_pivot_chain_ns")
+    return float(v.value)
 
 
 def save_tuning(path):

@@ -607,6 +607,26 @@ __global__ void tune_fill_kernel(double* ab, int64_t n, int64_t kk) {
   }
 }
 
+// One wave runs `steps` dependent steps of the factor's pivot chain -- the
+// reciprocal of the pivot (hardware estimate and two Newton steps, as the
+// diagonal-tile sweep takes it) and the fused multiply-add that forms the
+// next pivot from it -- between two reads of the 100 MHz real-time counter.
+// The values stay near the fixed point of d -> 2 - 0.25 / d.
+__global__ void pivot_chain_kernel(int64_t steps, double d0, double* out_d, unsigned long long* out_ticks) {
+  double d = d0;
+  const double p = 2.0, w = 0.5;
+  const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+  for (int64_t s = 0; s < steps; ++s) {
+    const double dinv = recip(d);
+    d = fma(-(w * w), dinv, p);
+  }
+  const unsigned long long t1 = __builtin_amdgcn_s_memrealtime();
+  if (threadIdx.x == 0) {
+    *out_d = d;
+    *out_ticks = t1 - t0;
+  }
+}
+
 // Schedules the measurement tries: the walk where it applies, then spine
 // workgroup counts up to the resident limit, and the rule's own count.
 std::vector<int> tune_candidates(int K) {
@@ -994,6 +1014,27 @@ void bandchol_batch_destroy(bandchol_batch_t p) {
   if (p->adj_mem) (void)hipFree(p->adj_mem);
   (void)hipSetDevice(cur);
   delete p;
+}
+
+int64_t bandchol_pivot_chain_ns(int64_t steps, double* ns_per_step) {
+  g_err[0] = 0;
+  if (steps < 1 || steps > ((int64_t)1 << 32)) return -1;
+  if (ns_per_step == nullptr) return -2;
+  hipStream_t st = g_stream;
+  void* buf = nullptr;
+  hipError_t e = hipMalloc(&buf, 256);
+  unsigned long long ticks = 0;
+  if (e == hipSuccess) {
+    pivot_chain_kernel<<<1, 64, 0, st>>>(steps, 1.9, (double*)buf, (unsigned long long*)((char*)buf + 64));
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&ticks, (char*)buf + 64, sizeof ticks, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (buf) (void)hipFree(buf);
+  if (e != hipSuccess) { set_err("pivot chain probe", e); return BANDCHOL_EHIP; }
+  *ns_per_step = (double)ticks * 10.0 / (double)steps;
+  return 0;
 }
 
 int64_t bandchol_set_walk_limit(int64_t kmax) {
