@@ -284,26 +284,35 @@ template <typename F>
 __device__ __forceinline__ void sweep_half(F (&row)[T], int j0, F& dcur, F& d_mine, int& fail) {
   const int lane = lane_id();
   constexpr int H = T / 2;
-  // Straight-line code (no exit per column) so that the scheduler can overlap
-  // column j+1's pivot chain with column j's row updates.
+  // Straight-line code (no exit per column).  Within a column the lane reads
+  // of its row updates go first, into distinct scalar registers, and the
+  // updates after them, so that the reads overlap instead of each waiting for
+  // the previous update; the next column's reciprocal is started before this
+  // column's updates (its inputs are known earlier), so that its latency hides
+  // behind them.
+  F dinv = recip(dcur);
 #pragma unroll
   for (int jj = 0; jj < H; ++jj) {
     const int j = j0 + jj;
     const F d = dcur;
     fail = (fail < 0 && !(d > F(0))) ? j : fail;
     const F w = row[j];
-    F p = F(0), wn = F(0);
-    if (jj + 1 < H) {
-      p = readlane(row[j + 1], j + 1);
-      wn = readlane(w, j + 1);
-    }
-    const F dinv = recip(d);
     d_mine = (lane == j) ? d : d_mine;
-    if (jj + 1 < H) dcur = fma(-(wn * wn), dinv, p);
     const F q = w * dinv;
+    F dinv_next = dinv;
+    if (jj + 1 < H) {
+      const F p = readlane(row[j + 1], j + 1);
+      const F wn = readlane(w, j + 1);
+      dcur = fma(-(wn * wn), dinv, p);
+      dinv_next = recip(dcur);
+    }
     row[j] = (lane == j) ? F(1) : q;
+    F wl[H];
 #pragma unroll
-    for (int l = j + 1; l < j0 + H; ++l) row[l] = fma(-q, readlane(w, l), row[l]);
+    for (int l = j + 1; l < j0 + H; ++l) wl[l - j0] = readlane(w, l);
+#pragma unroll
+    for (int l = j + 1; l < j0 + H; ++l) row[l] = fma(-q, wl[l - j0], row[l]);
+    dinv = dinv_next;
   }
 }
 
