@@ -427,6 +427,13 @@ def bench_batched(args):
         abs_d.append(torch.empty_like(ab0[-1]))
         bs_d.append(torch.empty_like(b0[-1]))
     t_gen = time.perf_counter() - t_gen
+    # the schedule per (n, k) bucket for this batch, measured (untimed): walk or tile
+    # schedule for its largest buckets, recorded in the batch table the plan reads
+    bc.batch_tune_clear()
+    t_tune = time.perf_counter()
+    tuned_ms = bc.batch_tune(ns, ks, reps=3, max_buckets=4)
+    t_tune = time.perf_counter() - t_tune
+    tuning = bc.batch_tune_entries()
     plan = bc.BatchPlan(ns, ks, abs_d, bs_d)
     info = torch.zeros(len(ns), dtype=torch.int64, device=dev)
 
@@ -494,7 +501,11 @@ def bench_batched(args):
         "config": {"workload": "batched band Cholesky factor + solve, %d systems, diagonally dominant SPD, "
                                "one HIP graph replay per step" % len(ns),
                    "batch": len(ns), "nrhs": nrhs, "sum_n": sum(ns), "flops_per_step": flops,
-                   "replay_ms_min": round(min(times), 4), "input_generation_s": round(t_gen, 2)},
+                   "replay_ms_min": round(min(times), 4), "input_generation_s": round(t_gen, 2),
+                   "autotuner": {"buckets_tried": tuning, "tuned_factor_ms": round(tuned_ms, 4),
+                                 "seconds": round(t_tune, 2),
+                                 "note": "wgs 1 = the walk in the persistent batch launch, more = the "
+                                         "multi-workgroup schedule for that bucket's systems; tile 32"}},
     }
     line["roofline"] = {"bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                         "frac": round(achieved / PEAK_FP64_TFLOPS, 5),
@@ -745,15 +756,25 @@ def bench_mixed(args):
         xh = x.cpu().numpy().reshape(n, nrhs, order="F")
         x64h = x64.cpu().numpy().reshape(n, nrhs, order="F")
         anrm = oracle.norm_inf(ab, k)
-        bwd = max(float(np.max(np.abs(b[:, c] - oracle.symv(ab, k, xh[:, c])))) /
-                  (anrm * float(np.max(np.abs(xh[:, c])))) for c in range(nrhs))
-        fwd = float(np.max(np.abs(xh - x64h)) / np.max(np.abs(x64h)))
+
+        def bwd_err(xx):
+            return max(float(np.max(np.abs(b[:, c] - oracle.symv(ab, k, xx[:, c])))) /
+                       (anrm * float(np.max(np.abs(xx[:, c])))) for c in range(nrhs))
+
+        # errors against the FP64 oracle's solution (column-order factor, threaded)
+        l_or, info_or = oracle.factor(ab, k, columns=True)
+        assert info_or == 0
+        x_or = oracle.solve(l_or, k, b)
+        kap = oracle.cond1_estimate(ab, l_or, k)
         m_ms, f_ms = float(np.median(ms_m)), float(np.median(ms_64))
         total_mixed += m_ms
         total_fp64 += f_ms
         per_d.append({"d": d, "mixed_ms": round(m_ms, 3), "fp64_factor_solve_ms": round(f_ms, 3),
-                      "iterations": it, "fallback": fb, "backward_error": bwd,
-                      "rel_diff_vs_fp64_solution": fwd, "fp64_info": int(info.item())})
+                      "iterations": it, "fallback": fb,
+                      "mixed_backward_error": bwd_err(xh), "fp64_backward_error": bwd_err(x64h),
+                      "mixed_forward_error_vs_oracle": float(np.max(np.abs(xh - x_or)) / np.max(np.abs(x_or))),
+                      "fp64_forward_error_vs_oracle": float(np.max(np.abs(x64h - x_or)) / np.max(np.abs(x_or))),
+                      "kappa1_estimate": kap, "fp64_info": int(info.item())})
         del dab, db, x, l, x64
         torch.cuda.empty_cache()
     line = {

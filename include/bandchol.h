@@ -342,6 +342,43 @@ int64_t bandchol_batch_backward(bandchol_batch_t plan, int64_t nrhs, void* strea
 /* Frees the plan's device memory (waits for the device first). */
 void bandchol_batch_destroy(bandchol_batch_t plan);
 
+/*
+ * Schedule per (n, k) bucket for the systems of batch plans (the tuning of the
+ * batched path).  Buckets as for bandchol_schedule.  In a batch, the systems
+ * the walk takes run side by side in one persistent launch, one workgroup
+ * each, while a system given w >= 2 workgroups is factored on its own with the
+ * multi-workgroup schedule after that launch; so the best choice for a
+ * bucket depends on the batch, and this table is kept apart from the
+ * single-matrix one.  A plan reads it when it is created: the bucket's entry
+ * if there is one, else the walk for K <= 15 and the single-matrix choice
+ * above (its rule where that choice is the walk).  The tile is T =
+ * bandchol_tile() for every choice: it is set by the 16 x 16 x 4 FP64 matrix
+ * instruction and the LDS the walk keeps per tile diagonal, not tuned.
+ *
+ * bandchol_batch_tune_set / _entries / _clear: as bandchol_tune_set /
+ * _entries / _clear, on this table.
+ *
+ * bandchol_batch_tune: measures, on the current device and the stream of
+ * bandchol_set_stream, the batched factor of systems of the given orders and
+ * bandwidths (HOST arrays of length batch; test bands generated on the
+ * device as for bandchol_tune_factor, 8 (k+1) n bytes each, allocated and
+ * freed by the call: not under stream capture).  Starting from the current
+ * table it takes the buckets in decreasing order of the walk's work estimate
+ * (n / T)(10 + K^2) summed over their systems, up to max_buckets of them,
+ * tries the other schedule for each (the multi-workgroup schedule with the
+ * rule's count where the bucket walks, the walk where it does not and K <=
+ * 15), and keeps it when the batch factor's median time over `reps` runs
+ * drops by more than 1 %; every bucket tried gets an entry with the choice
+ * kept.  *ms_out (may be NULL): the final median in ms.  Returns -1 batch < 1,
+ * -2 n (NULL or an n < 1), -3 k, -4 reps outside 1..1000, -5 max_buckets < 0,
+ * BANDCHOL_EHIP on a HIP error or a failed factor.  Synchronous.
+ */
+int64_t bandchol_batch_tune_set(int64_t n, int64_t k, int64_t wgs);
+int64_t bandchol_batch_tune_entries(int64_t cap, int64_t* n, int64_t* k, int64_t* wgs, double* ms);
+void bandchol_batch_tune_clear(void);
+int64_t bandchol_batch_tune(int64_t batch, const int64_t* n, const int64_t* k, int64_t reps, int64_t max_buckets,
+                            double* ms_out);
+
 #ifdef __cplusplus
 }
 #endif

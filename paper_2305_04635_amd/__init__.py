@@ -48,6 +48,10 @@ SIGNATURES = {
     "bandchol_tune_clear": (None, []),
     "bandchol_tune_factor": (_I64, [_I64, _I64, _I64, _VP, _VP]),
     "bandchol_pivot_chain_ns": (_I64, [_I64, _VP]),
+    "bandchol_batch_tune_set": (_I64, [_I64, _I64, _I64]),
+    "bandchol_batch_tune_entries": (_I64, [_I64, _VP, _VP, _VP, _VP]),
+    "bandchol_batch_tune_clear": (None, []),
+    "bandchol_batch_tune": (_I64, [_I64, _VP, _VP, _I64, _I64, _VP]),
 }
 
 EHIP = -1000
@@ -159,19 +163,61 @@ def pivot_chain_ns(steps=1 << 20):
     return float(v.value)
 
 
+def batch_tune_set(n, k, wgs):
+    """Record the schedule of the (n, k) bucket for batch plans (1 = walk, 0 removes it)."""
+    rc = int(load().bandchol_batch_tune_set(int(n), int(k), int(wgs)))
+    if rc != 0:
+        _raise(rc, "bandchol_batch_tune_set")
+
+
+def batch_tune_entries():
+    """The batch schedule table: a list of dicts with keys n, k, wgs, ms."""
+    lib = load()
+    count = int(lib.bandchol_batch_tune_entries(0, None, None, None, None))
+    if count == 0:
+        return []
+    n, k, w = (ctypes.c_int64 * count)(), (ctypes.c_int64 * count)(), (ctypes.c_int64 * count)()
+    ms = (ctypes.c_double * count)()
+    got = int(lib.bandchol_batch_tune_entries(count, n, k, w, ms))
+    return [{"n": n[i], "k": k[i], "wgs": w[i], "ms": ms[i]} for i in range(min(got, count))]
+
+
+def batch_tune_clear():
+    load().bandchol_batch_tune_clear()
+
+
+def batch_tune(ns, ks, reps=3, max_buckets=4):
+    """Measure the batched factor of systems of these shapes and settle the schedule of
+    its largest buckets in the batch table; returns the final median ms."""
+    lib = load()
+    lib.bandchol_set_stream(_stream())
+    b = len(ns)
+    I64 = ctypes.c_int64 * max(b, 1)
+    ms = ctypes.c_double(0.0)
+    rc = int(lib.bandchol_batch_tune(b, I64(*ns), I64(*ks), int(reps), int(max_buckets), ctypes.byref(ms)))
+    if rc != 0:
+        _raise(rc, "bandchol_batch_tune")
+    return float(ms.value)
+
+
 def save_tuning(path):
-    """Write the schedule table as JSON."""
+    """Write both schedule tables (single matrices and batches) as JSON."""
     import json
     with open(path, "w") as f:
-        json.dump(tune_entries(), f, indent=1)
+        json.dump({"single": tune_entries(), "batch": batch_tune_entries()}, f, indent=1)
 
 
 def load_tuning(path):
-    """Add the entries of a JSON schedule table written by save_tuning."""
+    """Add the entries of JSON schedule tables written by save_tuning (a plain list is
+    read as the single-matrix table)."""
     import json
     with open(path) as f:
-        for e in json.load(f):
-            tune_set(e["n"], e["k"], e["wgs"])
+        d = json.load(f)
+    single, batch = (d, []) if isinstance(d, list) else (d.get("single", []), d.get("batch", []))
+    for e in single:
+        tune_set(e["n"], e["k"], e["wgs"])
+    for e in batch:
+        batch_tune_set(e["n"], e["k"], e["wgs"])
 
 
 def factor(ab, n, k, ldab=None):

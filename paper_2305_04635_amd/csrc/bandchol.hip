@@ -226,6 +226,40 @@ int schedule_wgs(int64_t n, int K) {
   return spine_rule(K);
 }
 
+// The batch table: the same buckets, for systems of a batch plan.  There the
+// walk of one system runs beside the walks of all the others in one
+// persistent launch, while a system given to the multi-workgroup schedule is
+// factored on its own after it, so the best choice differs from that of a
+// single matrix; it is kept apart.  Without an entry a batch walks every
+// system the walk takes (K <= 15) and gives the others the single-matrix
+// choice.
+std::vector<TuneEntry> g_btune;
+
+int batch_schedule_wgs(int64_t n, int K) {
+  const int nb = n_bucket(n);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const TuneEntry& t : g_btune)
+      if (t.nb == nb && t.K == K) return t.wgs;
+  }
+  if (K <= WALK_KMAX) return 1;
+  const int w = schedule_wgs(n, K);
+  return w == 1 ? spine_rule(K) : w;
+}
+
+void btune_record(int64_t n, int64_t kk, int K, int wgs, double ms) {
+  const int nb = n_bucket(n);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (TuneEntry& t : g_btune)
+    if (t.nb == nb && t.K == K) {
+      t.wgs = wgs, t.n = n, t.k = kk, t.ms = ms;
+      return;
+    }
+  TuneEntry t;
+  t.nb = nb, t.K = K, t.wgs = wgs, t.n = n, t.k = kk, t.ms = ms;
+  g_btune.push_back(t);
+}
+
 // Spine workgroup count after the BANDCHOL_MAX_WG cap (testing aid).
 int spine_grid(int want) {
   int grid = want < 2 ? 2 : want;
@@ -831,7 +865,8 @@ int64_t bandchol_batch_create(int64_t batch, const int64_t* n, const int64_t* k,
     const int64_t kk = k[i] < n[i] - 1 ? k[i] : (n[i] > 0 ? n[i] - 1 : 0);
     const int K = tile_diagonals(n[i], k[i]);
     WalkSys w{ab[i], n[i], kk, ldab[i], nullptr, b ? b[i] : nullptr, b ? ldb[i] : 0};
-    if (K <= WALK_KMAX) {
+    const int bw = batch_schedule_wgs(n[i], K);
+    if (bw == 1 && K <= WALK_KMAX) {
       p->walk.push_back(w);
       p->walk_id.push_back(i);
       p->walk_kmax = std::max(p->walk_kmax, K);
@@ -840,7 +875,7 @@ int64_t bandchol_batch_create(int64_t batch, const int64_t* n, const int64_t* k,
     } else {
       p->wide.push_back(w);
       p->wide_id.push_back(i);
-      p->wide_wgs.push_back(schedule_wgs(n[i], K));
+      p->wide_wgs.push_back(bw);
       wide_ws = std::max(wide_ws, std::max(bandchol_factor2_workspace(n[i], K), bandchol_solve_workspace(n[i], kk)));
     }
   }
@@ -1014,6 +1049,160 @@ void bandchol_batch_destroy(bandchol_batch_t p) {
   if (p->adj_mem) (void)hipFree(p->adj_mem);
   (void)hipSetDevice(cur);
   delete p;
+}
+
+int64_t bandchol_batch_tune_set(int64_t n, int64_t k, int64_t wgs) {
+  g_err[0] = 0;
+  if (n < 1 || n > ((int64_t)1 << 31) - T) return -1;
+  if (k < 0) return -2;
+  const int K = tile_diagonals(n, k);
+  if (wgs < 0 || (wgs == 1 && K > WALK_KMAX) || (wgs > 1 && K == 0) || wgs > resident_wgs()) return -3;
+  const int nb = n_bucket(n);
+  if (wgs == 0) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_btune.erase(std::remove_if(g_btune.begin(), g_btune.end(),
+                                 [&](const TuneEntry& t) { return t.nb == nb && t.K == K; }),
+                  g_btune.end());
+    return 0;
+  }
+  btune_record(n, k < n - 1 ? k : n - 1, K, (int)wgs, 0.0);
+  return 0;
+}
+
+int64_t bandchol_batch_tune_entries(int64_t cap, int64_t* n, int64_t* k, int64_t* wgs, double* ms) {
+  g_err[0] = 0;
+  if (cap < 0) return -1;
+  if (cap > 0 && n == nullptr) return -2;
+  if (cap > 0 && k == nullptr) return -3;
+  if (cap > 0 && wgs == nullptr) return -4;
+  if (cap > 0 && ms == nullptr) return -5;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  const int64_t count = (int64_t)g_btune.size();
+  for (int64_t i = 0; i < count && i < cap; ++i) {
+    n[i] = g_btune[i].n;
+    k[i] = g_btune[i].k;
+    wgs[i] = g_btune[i].wgs;
+    ms[i] = g_btune[i].ms;
+  }
+  return count;
+}
+
+void bandchol_batch_tune_clear(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_btune.clear();
+}
+
+int64_t bandchol_batch_tune(int64_t batch, const int64_t* n, const int64_t* k, int64_t reps, int64_t max_buckets,
+                            double* ms_out) {
+  g_err[0] = 0;
+  if (batch < 1) return -1;
+  if (n == nullptr) return -2;
+  if (k == nullptr) return -3;
+  if (reps < 1 || reps > 1000) return -4;
+  if (max_buckets < 0) return -5;
+  for (int64_t i = 0; i < batch; ++i) {
+    if (n[i] < 1 || n[i] > ((int64_t)1 << 31) - T) return -2;
+    if (k[i] < 0) return -3;
+  }
+  // the test bands: diagonally dominant, generated on the device, one allocation
+  std::vector<int64_t> kk(batch), ld(batch), off(batch);
+  size_t total = 0;
+  for (int64_t i = 0; i < batch; ++i) {
+    kk[i] = k[i] < n[i] - 1 ? k[i] : n[i] - 1;
+    ld[i] = kk[i] + 1;
+    off[i] = (int64_t)total;
+    total += (size_t)ld[i] * (size_t)n[i];
+  }
+  hipStream_t st = g_stream;
+  double* mem = nullptr;
+  int64_t* d_info = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipMalloc(&mem, sizeof(double) * total);
+  if (e == hipSuccess) e = hipMalloc(&d_info, sizeof(int64_t) * batch);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  std::vector<double*> ab(batch);
+  for (int64_t i = 0; i < batch; ++i) ab[i] = mem + off[i];
+  std::vector<int64_t> h_info(batch);
+  int64_t rc = 0;
+  // median factor time of a plan built from the current batch table; < 0 on failure
+  auto measure = [&]() -> double {
+    bandchol_batch_t plan = nullptr;
+    rc = bandchol_batch_create(batch, n, kk.data(), ab.data(), ld.data(), nullptr, nullptr, &plan);
+    if (rc != 0) return -1.0;
+    std::vector<float> t;
+    for (int64_t r = 0; r <= reps && e == hipSuccess; ++r) {
+      for (int64_t i = 0; i < batch && e == hipSuccess; ++i) {
+        const int64_t cnt = ld[i] * n[i];
+        tune_fill_kernel<<<(unsigned)std::min<int64_t>((cnt + 255) / 256, 8192), 256, 0, st>>>(ab[i], n[i], kk[i]);
+        e = hipGetLastError();
+      }
+      if (e == hipSuccess) e = hipEventRecord(e0, st);
+      if (e != hipSuccess) break;
+      rc = bandchol_batch_factor(plan, d_info, st);
+      if (rc != 0) break;
+      e = hipEventRecord(e1, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e == hipSuccess && r > 0) t.push_back(ms);
+    }
+    if (e == hipSuccess && rc == 0)
+      e = hipMemcpy(h_info.data(), d_info, sizeof(int64_t) * batch, hipMemcpyDeviceToHost);
+    bandchol_batch_destroy(plan);
+    if (e != hipSuccess || rc != 0) return -1.0;
+    for (int64_t i = 0; i < batch; ++i)
+      if (h_info[i] != 0) {
+        snprintf(g_err, sizeof g_err, "batch tune: factor of test system %lld returned info %lld", (long long)i,
+                 (long long)h_info[i]);
+        rc = BANDCHOL_EHIP;
+        return -1.0;
+      }
+    std::sort(t.begin(), t.end());
+    return t[t.size() / 2];
+  };
+  double best = e == hipSuccess ? measure() : -1.0;
+  if (best >= 0.0) {
+    // buckets by the walk's work estimate, largest first
+    struct Bucket { int nb, K; int64_t n, k; double work; };
+    std::vector<Bucket> bk;
+    for (int64_t i = 0; i < batch; ++i) {
+      const int K = tile_diagonals(n[i], kk[i]), nb = n_bucket(n[i]);
+      const double w = (double)((n[i] + T - 1) / T) * (10.0 + (double)K * K);
+      bool found = false;
+      for (Bucket& b : bk)
+        if (b.nb == nb && b.K == K) { b.work += w; found = true; break; }
+      if (!found) bk.push_back(Bucket{nb, K, n[i], kk[i], w});
+    }
+    std::stable_sort(bk.begin(), bk.end(), [](const Bucket& x, const Bucket& y) { return x.work > y.work; });
+    for (size_t b = 0; b < bk.size() && (int64_t)b < max_buckets && best >= 0.0; ++b) {
+      if (bk[b].K == 0) continue;
+      const int cur = batch_schedule_wgs(bk[b].n, bk[b].K);
+      int alt = cur == 1 ? spine_rule(bk[b].K) : (bk[b].K <= WALK_KMAX ? 1 : 0);
+      if (alt == 0) continue;
+      btune_record(bk[b].n, bk[b].k, bk[b].K, alt, 0.0);
+      const double t = measure();
+      if (t < 0.0) { best = -1.0; break; }
+      if (t < 0.99 * best) {
+        best = t;
+        btune_record(bk[b].n, bk[b].k, bk[b].K, alt, t);
+      } else {
+        btune_record(bk[b].n, bk[b].k, bk[b].K, cur, best);
+      }
+    }
+  }
+  if (e != hipSuccess) {
+    set_err("batch tune", e);
+    rc = BANDCHOL_EHIP;
+  } else if (best < 0.0 && rc == 0) {
+    rc = BANDCHOL_EHIP;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (d_info) (void)hipFree(d_info);
+  if (mem) (void)hipFree(mem);
+  if (rc == 0 && ms_out) *ms_out = best;
+  return rc;
 }
 
 int64_t bandchol_pivot_chain_ns(int64_t steps, double* ns_per_step) {

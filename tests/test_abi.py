@@ -189,3 +189,42 @@ def test_schedule_rule_and_table_on_host(tmp_path, monkeypatch):
     finally:
         bc.tune_clear()
         bc.set_walk_limit(prev)
+
+
+def test_batch_schedule_table_on_host(tmp_path):
+    """The batch plans' schedule table: entries per bucket, JSON round trip
+    together with the single-matrix table, argument checks (no GPU work)."""
+    lib = bc.load()
+    bc.batch_tune_clear()
+    bc.tune_clear()
+    try:
+        bc.batch_tune_set(20000, 256, 64)             # bucket (14, 8): the tile schedule
+        bc.batch_tune_set(17000, 250, 1)              # same bucket: replaced by the walk
+        bc.batch_tune_set(3000, 100, 2)
+        assert sorted((e["n"], e["k"], e["wgs"]) for e in bc.batch_tune_entries()) == \
+            [(3000, 100, 2), (17000, 250, 1)]
+        assert bc.tune_entries() == []                # the single-matrix table is apart
+        bc.tune_set(100000, 1000, 384)
+        path = str(tmp_path / "tuning.json")
+        bc.save_tuning(path)
+        bc.batch_tune_clear()
+        bc.tune_clear()
+        bc.load_tuning(path)
+        assert len(bc.batch_tune_entries()) == 2 and len(bc.tune_entries()) == 1
+        bc.batch_tune_set(3000, 100, 0)
+        assert [e["k"] for e in bc.batch_tune_entries()] == [250]
+        assert lib.bandchol_batch_tune_set(100000, 1000, 1) == -3   # K = 32: no walk
+        assert lib.bandchol_batch_tune_set(1000, 0, 64) == -3       # K = 0: walk only
+        assert lib.bandchol_batch_tune_set(0, 1, 1) == -1
+        assert lib.bandchol_batch_tune_set(10, -1, 1) == -2
+        assert lib.bandchol_batch_tune_entries(1, None, None, None, None) == -2
+        I64 = ctypes.c_int64 * 2
+        assert lib.bandchol_batch_tune(0, I64(10, 20), I64(1, 2), 1, 1, None) == -1
+        assert lib.bandchol_batch_tune(2, None, I64(1, 2), 1, 1, None) == -2
+        assert lib.bandchol_batch_tune(2, I64(10, 0), I64(1, 2), 1, 1, None) == -2
+        assert lib.bandchol_batch_tune(2, I64(10, 20), I64(1, -2), 1, 1, None) == -3
+        assert lib.bandchol_batch_tune(2, I64(10, 20), I64(1, 2), 0, 1, None) == -4
+        assert lib.bandchol_batch_tune(2, I64(10, 20), I64(1, 2), 1, -1, None) == -5
+    finally:
+        bc.batch_tune_clear()
+        bc.tune_clear()
