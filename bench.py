@@ -127,8 +127,8 @@ def cpu_baseline(ks, n_sample, seed0):
     }
 
 
-# sources of the batched factor kernel (walk_batch_kernel) and of the plan that launches it
-BATCH_KERNEL_SOURCES = ("walk.hip", "common.h", "bandchol.hip")
+# sources of the batched factor kernel (walk_batch_kernel)
+BATCH_KERNEL_SOURCES = ("walk.hip", "common.h")
 
 
 def source_hash_of(files):
@@ -168,7 +168,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the accuracy checks after timing")
     ap.add_argument("--no-fwd-bwd", action="store_true", help="skip the forward+backward (reverse-mode) leg")
-    ap.add_argument("--workload", choices=("sweep", "batched", "adjoint", "mixed"), default="sweep")
+    ap.add_argument("--workload", choices=("sweep", "batched", "adjoint", "mixed", "spine-profile"), default="sweep")
     ap.add_argument("--batch", type=int, default=512)
     args = ap.parse_args()
 
@@ -189,6 +189,8 @@ def main():
         return bench_adjoint(args)
     if args.workload == "mixed":
         return bench_mixed(args)
+    if args.workload == "spine-profile":
+        return bench_spine_profile(args)
     ks = [int(x) for x in args.ks.split(",")]
     n, nrhs = args.n, args.nrhs
     dev = torch.device("cuda:0")
@@ -785,6 +787,39 @@ def bench_mixed(args):
         "config": {"workload": "mixed-precision solve, n=%d, k=%d, nrhs=%d, A = L0 L0^T + 10^(-2d)||A|| I, "
                                "L0 diagonal 10^U[-d,0], d = 1..5" % (n, k, nrhs),
                    "fp64_factor_solve_ms_sum": round(total_fp64, 3), "per_d": per_d},
+    }
+    print(json.dumps(line))
+
+
+def bench_spine_profile(args):
+    """Where the diagonal chain's step goes, per k of the sweep (n = args.n): shader-clock
+    cycles per 32-column step of each phase of the spine (bandchol_spine_profile), the
+    clock rate they imply, and the pivot chain's floor per step for comparison."""
+    import torch
+
+    import paper_2305_04635_amd as bc
+    torch.cuda.set_device(0)
+    bc.load()
+    ks = [int(x) for x in args.ks.split(",")]
+    pivot_ns = bc.pivot_chain_ns(1 << 20)
+    per_k = []
+    for k in ks:
+        d = bc.spine_profile(args.n, k, reps=3)
+        w0 = d["sweep"] + d["w0_wait"] + d["phase_b"] + d["phase_c"]
+        d["k"] = k
+        d["w0_step_cycles"] = w0
+        d["clock_ghz"] = w0 * d["steps"] / (d["factor_ms"] * 1e-3) / 1e9
+        d["step_us"] = d["factor_ms"] * 1e3 / max(d["steps"], 1)
+        d["chain_floor_per_step_us"] = 32 * pivot_ns * 1e-3
+        per_k.append({key: (round(v, 4) if isinstance(v, float) else v) for key, v in d.items()})
+    line = {
+        "metric": "spine step breakdown (shader-clock cycles per 32-column step), n=%d" % args.n,
+        "value": round(sum(p["step_us"] for p in per_k) / len(per_k), 4), "unit": "us per step (mean over k)",
+        "n_gpus": 1, "steps": 3, "warmup": 0, "ms_per_step": None, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic (diagonally dominant band generated on the device)",
+        "config": {"workload": "FP64 factor, n=%d, k in {%s}, spine phases timed with s_memtime"
+                               % (args.n, ",".join(map(str, ks))), "pivot_chain_ns": round(pivot_ns, 3),
+                   "per_k": per_k},
     }
     print(json.dumps(line))
 

@@ -157,6 +157,21 @@ int64_t bandchol_set_walk_limit(int64_t kmax);
 int64_t bandchol_pivot_chain_ns(int64_t steps, double* ns_per_step);
 
 /*
+ * Where the time of the diagonal chain goes: factors an (n, k) band (generated
+ * on the device as for bandchol_tune_factor) `reps` times with the
+ * multi-workgroup schedule (the workgroup count the factor would use, its
+ * rule where that is the walk) and the spine's phase times recorded (shader
+ * clock, s_memtime), and writes out[0..12]: per step of 32 columns, the cycles
+ * of wave 0's diagonal-tile sweep (0), its wait for waves 1-3 at the end of
+ * phase A (1), phase B (2), phase C (3); for waves 1, 2, 3 the cycles of
+ * their phase-A work and of their wait at its end (4..9); the number of steps
+ * (10); the last factor's time in ms (11); its workgroup count (12).  n >= 2
+ * (-1), k >= 1 (-2), 1 <= reps <= 100 (-3), out with cap >= 13 (-4).
+ * Allocates the test band; synchronous; not under stream capture.
+ */
+int64_t bandchol_spine_profile(int64_t n, int64_t k, int64_t reps, double* out, int64_t cap);
+
+/*
  * Schedule per (n, k) bucket.  The paper picks the dimension of its block
  * grid per problem with a heuristic (block size near 50, no more blocks than
  * cores) and lets users who know their bandwidths and hardware tune it

@@ -48,6 +48,7 @@ SIGNATURES = {
     "bandchol_tune_clear": (None, []),
     "bandchol_tune_factor": (_I64, [_I64, _I64, _I64, _VP, _VP]),
     "bandchol_pivot_chain_ns": (_I64, [_I64, _VP]),
+    "bandchol_spine_profile": (_I64, [_I64, _I64, _I64, _VP, _I64]),
     "bandchol_batch_tune_set": (_I64, [_I64, _I64, _I64]),
     "bandchol_batch_tune_entries": (_I64, [_I64, _VP, _VP, _VP, _VP]),
     "bandchol_batch_tune_clear": (None, []),
@@ -198,6 +199,23 @@ def batch_tune(ns, ks, reps=3, max_buckets=4):
     if rc != 0:
         _raise(rc, "bandchol_batch_tune")
     return float(ms.value)
+
+
+SPINE_PROFILE_KEYS = ("sweep", "w0_wait", "phase_b", "phase_c", "w1_work", "w1_wait", "w2_work", "w2_wait",
+                      "w3_work", "w3_wait")
+
+
+def spine_profile(n, k, reps=3):
+    """Cycles per 32-column step of the diagonal chain's phases (see bandchol_spine_profile)."""
+    lib = load()
+    lib.bandchol_set_stream(_stream())
+    out = (ctypes.c_double * 13)()
+    rc = int(lib.bandchol_spine_profile(int(n), int(k), int(reps), out, 13))
+    if rc != 0:
+        _raise(rc, "bandchol_spine_profile")
+    d = {key: out[i] for i, key in enumerate(SPINE_PROFILE_KEYS)}
+    d.update(steps=int(out[10]), factor_ms=out[11], workgroups=int(out[12]))
+    return d
 
 
 def save_tuning(path):

@@ -39,6 +39,8 @@ hipError_t bandchol_factor2_launch_f32(int64_t n, int64_t k, float* ab, int64_t 
                                        int grid_max, hipStream_t st);
 hipError_t bandchol_factor2_launch(int64_t n, int64_t k, double* ab, int64_t ldab, int64_t* d_info, void* ws,
                                    int grid_max, hipStream_t st);
+hipError_t bandchol_factor2_launch_profiled(int64_t n, int64_t k, double* ab, int64_t ldab, int64_t* d_info, void* ws,
+                                            int grid_max, unsigned long long* prof, hipStream_t st);
 hipError_t bandchol_solve_launch(int64_t n, int64_t k, int64_t nrhs, const double* ab, int64_t ldab, double* b,
                                  int64_t ldb, void* ws, int num_cus, int64_t* d_status, hipStream_t st);
 
@@ -1203,6 +1205,60 @@ int64_t bandchol_batch_tune(int64_t batch, const int64_t* n, const int64_t* k, i
   if (mem) (void)hipFree(mem);
   if (rc == 0 && ms_out) *ms_out = best;
   return rc;
+}
+
+int64_t bandchol_spine_profile(int64_t n, int64_t k, int64_t reps, double* out, int64_t cap) {
+  g_err[0] = 0;
+  constexpr int SLOTS = 11;   // as the factor kernel's PROF_* slots
+  if (n < 2 || n > ((int64_t)1 << 31) - T) return -1;
+  if (k < 1) return -2;
+  if (reps < 1 || reps > 100) return -3;
+  if (out == nullptr || cap < SLOTS + 2) return -4;
+  const int64_t kk = k < n - 1 ? k : n - 1;
+  const int K = tile_diagonals(n, kk);
+  int wgs = schedule_wgs(n, K);
+  if (wgs == 1) wgs = spine_rule(K);
+  hipStream_t st = g_stream;
+  double* ab = nullptr;
+  void* buf = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipMalloc(&ab, sizeof(double) * (size_t)(kk + 1) * (size_t)n);
+  if (e == hipSuccess) e = hipMalloc(&buf, 512);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  void* ws = e == hipSuccess ? workspace(bandchol_factor2_workspace(n, K), &e) : nullptr;
+  int64_t* d_info = (int64_t*)buf;
+  unsigned long long* prof = (unsigned long long*)((char*)buf + 256);
+  const int64_t total = (kk + 1) * n;
+  float ms = 0.0f;
+  for (int64_t r = 0; r < reps && e == hipSuccess; ++r) {
+    tune_fill_kernel<<<(unsigned)std::min<int64_t>((total + 255) / 256, 8192), 256, 0, st>>>(ab, n, kk);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    if (e == hipSuccess) e = bandchol_factor2_launch_profiled(n, kk, ab, kk + 1, d_info, ws, spine_grid(wgs), prof, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  }
+  unsigned long long h[SLOTS] = {};
+  int64_t info = 0;
+  if (e == hipSuccess) e = hipMemcpy(h, prof, sizeof h, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(&info, d_info, sizeof info, hipMemcpyDeviceToHost);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (buf) (void)hipFree(buf);
+  if (ab) (void)hipFree(ab);
+  if (e != hipSuccess) { set_err("spine profile", e); return BANDCHOL_EHIP; }
+  if (info != 0) {
+    snprintf(g_err, sizeof g_err, "spine profile: factor returned info %lld", (long long)info);
+    return BANDCHOL_EHIP;
+  }
+  const double steps = h[SLOTS - 1] > 0 ? (double)h[SLOTS - 1] : 1.0;
+  for (int i = 0; i < SLOTS - 1; ++i) out[i] = (double)h[i] / steps;
+  out[SLOTS - 1] = (double)h[SLOTS - 1];
+  out[SLOTS] = ms;
+  out[SLOTS + 1] = wgs;
+  return 0;
 }
 
 int64_t bandchol_pivot_chain_ns(int64_t steps, double* ns_per_step) {

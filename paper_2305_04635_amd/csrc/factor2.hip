@@ -52,7 +52,16 @@ struct Ws {
   unsigned long long* first_fail;
   glb_i* spine_cu;  // the spine's CU (cu_ident), -1 before it starts
   const glb_t<F>* zero;  // a zero: masked-off lanes load it, so that operand loads are unconditional
+  unsigned long long* prof;  // if not null: the spine's phase times, summed over the steps (s_memtime)
 };
+
+// Slots of Ws::prof: wave 0's sweep, its wait at the end of phase A, phases B
+// and C; per wave w = 1..3 its phase-A work and its wait at the end of phase A;
+// the number of steps summed.
+enum { PROF_SWEEP, PROF_W0_WAIT, PROF_B, PROF_C, PROF_W1_WORK, PROF_W1_WAIT, PROF_W2_WORK, PROF_W2_WAIT,
+       PROF_W3_WORK, PROF_W3_WAIT, PROF_STEPS, PROF_SLOTS };
+
+__device__ __forceinline__ unsigned long long stamp(bool on) { return on ? __builtin_amdgcn_s_memtime() : 0ull; }
 
 template <typename F>
 struct Args {
@@ -783,18 +792,30 @@ __device__ __attribute__((noinline)) void spine_wave0(const Args<F>& A_, const S
   const Args<F> A = A_;
   SpineLds<F> S = S_;
   const BandT<F>& a = A.a;
+  const bool prof = A.w.prof != nullptr;
+  unsigned long long p_sweep = 0, p_wait = 0, p_b = 0, p_c = 0, steps = 0;
   for (int64_t C = 0; C < A.NB; ++C) {
     const bool next = C + 1 < A.NB;
+    const unsigned long long t0 = stamp(prof);
     // phase A
     spine_sweep<F>(S.diag, S.sd, S.linvt, S.linvt_prev, A.w.linvt + (C - 1) * T * T,
                    C >= 1 ? &A.w.tflag[tidx(A, C - 1, C - 1)] : nullptr, C, a.n, A.w.first_fail, A.w.abort_flag,
                    s_fail);
+    const unsigned long long t1 = stamp(prof);
     lds_barrier();
-    if (*s_fail != -1 || !next) return;
+    const unsigned long long t2 = stamp(prof);
+    if (*s_fail != -1 || !next) {
+      if (prof && lane_id() == 0) {
+        A.w.prof[PROF_SWEEP] = p_sweep, A.w.prof[PROF_W0_WAIT] = p_wait, A.w.prof[PROF_B] = p_b;
+        A.w.prof[PROF_C] = p_c, A.w.prof[PROF_STEPS] = steps;
+      }
+      return;
+    }
     // phase B: block (0, 0) of L(C+1, C) = acco * L(C,C)^{-T}; wave 1 stores it
     // during the next step
     if (A.K >= 1) blk_to_lds(S.lcur, 0, 0, blk_trsm_lds(S.acco, S.linvt, 0, 0, LP));
     lds_barrier();
+    const unsigned long long t3 = stamp(prof);
     // phase C: block (0, 0) of the next diagonal tile, staged in acco's buffer
     v4_t<F> acc = blk_from_lds<F>(S.accd, 0, 0);
     if (A.K >= 1) acc = blk_gemm_lds<F>(S.lcur, S.lcur, 0, 0, acc);
@@ -805,6 +826,10 @@ __device__ __attribute__((noinline)) void spine_wave0(const Args<F>& A_, const S
     t = S.l2prev; S.l2prev = S.l2cur; S.l2cur = t;
     t = S.linvt_prev; S.linvt_prev = S.linvt; S.linvt = t;
     lds_barrier();
+    if (prof) {
+      const unsigned long long t4 = stamp(true);
+      p_sweep += t1 - t0, p_wait += t2 - t1, p_b += t3 - t2, p_c += t4 - t3, steps += 1;
+    }
   }
 }
 
@@ -816,11 +841,19 @@ __device__ __attribute__((noinline)) void spine_waves123(const Args<F>& A_, cons
   const BandT<F>& a = A.a;
   const int wave = wave_id();
   int early = 0;
+  const bool prof = A.w.prof != nullptr;
+  unsigned long long p_work = 0, p_wait = 0;
   for (int64_t C = 0; C < A.NB; ++C) {
     const bool next = C + 1 < A.NB;
+    const unsigned long long t0 = stamp(prof);
     // phase A
     spine_prepare(A, C, S, next, sync, s_pub, s_fail, early);
+    const unsigned long long t1 = stamp(prof);
     lds_barrier();
+    if (prof) {
+      p_work += t1 - t0, p_wait += stamp(true) - t1;
+      if (!next && lane_id() == 0) A.w.prof[PROF_W1_WORK + 2 * (wave - 1)] = p_work, A.w.prof[PROF_W1_WAIT + 2 * (wave - 1)] = p_wait;
+    }
     if (*s_fail != -1) return;
     if (!next) {
       if (wave == 1) store_lcc(S.diag, C, a);
@@ -994,7 +1027,7 @@ size_t bandchol_factor2_workspace_f32(int64_t n, int64_t K) { return factor2_wor
 
 template <typename F>
 static hipError_t factor2_launch(int64_t n, int64_t k, F* ab, int64_t ldab, int64_t* d_info, void* ws, int grid_max,
-                                 hipStream_t st) {
+                                 hipStream_t st, unsigned long long* prof = nullptr) {
   using namespace bandchol_f2;
   const int NB = (int)((n + T - 1) / T);
   int K = (int)((k + T - 1) / T);
@@ -1009,6 +1042,7 @@ static hipError_t factor2_launch(int64_t n, int64_t k, F* ab, int64_t ldab, int6
   A.w.first_fail = (unsigned long long*)(base + 16);
   A.w.spine_cu = (glb_i*)(base + 24);
   A.w.zero = (const glb_t<F>*)(base + 64);
+  A.w.prof = prof;
   A.w.tflag = (glb_i*)(base + 256);
   A.w.hflag = A.w.tflag + (size_t)NB * (K + 1);
   A.w.pflag = A.w.hflag + NB;
@@ -1030,6 +1064,12 @@ static hipError_t factor2_launch(int64_t n, int64_t k, F* ab, int64_t ldab, int6
 hipError_t bandchol_factor2_launch(int64_t n, int64_t k, double* ab, int64_t ldab, int64_t* d_info, void* ws,
                                    int grid_max, hipStream_t st) {
   return factor2_launch<double>(n, k, ab, ldab, d_info, ws, grid_max, st);
+}
+
+// The FP64 factor with the spine's phase times summed into prof (PROF_SLOTS values).
+hipError_t bandchol_factor2_launch_profiled(int64_t n, int64_t k, double* ab, int64_t ldab, int64_t* d_info, void* ws,
+                                            int grid_max, unsigned long long* prof, hipStream_t st) {
+  return factor2_launch<double>(n, k, ab, ldab, d_info, ws, grid_max, st, prof);
 }
 
 hipError_t bandchol_factor2_launch_f32(int64_t n, int64_t k, float* ab, int64_t ldab, int64_t* d_info, void* ws,

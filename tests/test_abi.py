@@ -228,3 +228,16 @@ def test_batch_schedule_table_on_host(tmp_path):
     finally:
         bc.batch_tune_clear()
         bc.tune_clear()
+
+
+def test_spine_profile_bad_arguments_on_host():
+    lib = bc.load()
+    out = (ctypes.c_double * 13)()
+    assert lib.bandchol_spine_profile(1, 10, 1, out, 13) == -1
+    assert lib.bandchol_spine_profile(100, 0, 1, out, 13) == -2
+    assert lib.bandchol_spine_profile(100, 10, 0, out, 13) == -3
+    assert lib.bandchol_spine_profile(100, 10, 1, None, 13) == -4
+    assert lib.bandchol_spine_profile(100, 10, 1, out, 12) == -4
+    assert lib.bandchol_pivot_chain_ns(0, None) == -1
+    v = ctypes.c_double()
+    assert lib.bandchol_pivot_chain_ns(10, None) == -2

@@ -112,3 +112,23 @@ def test_batch_plan_takes_the_table_entry(empty_table):
     for (n, k), a, d in zip(shapes, abs_h, abs_d):
         l_gpu = from_dev(d, a.shape)
         assert oracle.llt_residual(l_gpu, a, k) <= ETA_TOL
+
+
+@pytest.mark.parametrize("k", [50, 700])
+def test_spine_profile_accounts_for_the_step(k):
+    """The spine's phase times (s_memtime) add up: wave 0's four phases cover
+    its whole step, waves 1-3 are in step with it, and the implied shader
+    clock is a plausible one; the pivot-chain probe is far below a step."""
+    import paper_2305_04635_amd as bc
+    n = 20000
+    d = bc.spine_profile(n, k, reps=2)
+    nb = (n + 31) // 32
+    assert d["steps"] == nb - 1
+    w0 = d["sweep"] + d["w0_wait"] + d["phase_b"] + d["phase_c"]
+    ghz = w0 * d["steps"] / (d["factor_ms"] * 1e-3) / 1e9
+    assert 0.5 < ghz < 3.5, ghz
+    for w in (1, 2, 3):
+        # the phase-A work and wait of waves 1-3 span wave 0's phase A
+        assert abs(d["w%d_work" % w] + d["w%d_wait" % w] - (d["sweep"] + d["w0_wait"])) < 0.25 * w0
+    ns = bc.pivot_chain_ns(1 << 16)
+    assert 1.0 < ns < 1000.0 and 32 * ns * 1e-9 < d["factor_ms"] * 1e-3 / d["steps"]
