@@ -429,8 +429,11 @@ __global__ void __launch_bounds__(NT) solve_kernel(SolveArgs S) {
     } else {
       // forward: B = ST+1 .. NB-1; back: B = NB-ST-2 .. 0
       const int B = FWD ? ST + t : S.NB - ST - 1 - t;
-      const bool ok = S.nrhs == 1 ? helper<ST, FWD, 2, 1>(S, B, (lds_i*)&s_flag)
-                                  : helper<ST, FWD, 1, RHS_MAX>(S, B, (lds_i*)&s_flag);
+      // helpers sized to the pass's right-hand sides (the missing ones would read zeros)
+      const bool ok = S.nrhs == 1   ? helper<ST, FWD, 2, 1>(S, B, (lds_i*)&s_flag)
+                      : S.nrhs == 2 ? helper<ST, FWD, 2, 2>(S, B, (lds_i*)&s_flag)
+                      : S.nrhs <= 4 ? helper<ST, FWD, 1, 4>(S, B, (lds_i*)&s_flag)
+                                    : helper<ST, FWD, 1, RHS_MAX>(S, B, (lds_i*)&s_flag);
       if (!ok) break;
     }
     if (s_flag) break;
