@@ -279,7 +279,12 @@ __device__ __forceinline__ v4_t<F> blk_trsm_lds(const lds_t<F>* x, const lds_t<F
 //
 // Afterwards lane i < T holds row i of L (upper part unspecified) and lane
 // T+b holds row b of L^{-T}.  Returns the first local column whose pivot is
-// not > 0 (zero, negative or NaN), or -1.
+// not > 0 (zero, negative or NaN), or -1, found once at the end from the
+// pivots kept per lane (after a failed pivot the later columns are garbage,
+// which only the failure report sees).  The unit diagonal of the unit factor
+// is left as d_j (1 / d_j) rather than set to 1: within the reciprocal's last
+// bit of 1, exactly 1 for pivots that are powers of two, and no select per
+// column.
 template <typename F>
 __device__ __forceinline__ void sweep_half(F (&row)[T], int j0, F& dcur, F& d_mine, int& fail) {
   const int lane = lane_id();
@@ -295,7 +300,6 @@ __device__ __forceinline__ void sweep_half(F (&row)[T], int j0, F& dcur, F& d_mi
   for (int jj = 0; jj < H; ++jj) {
     const int j = j0 + jj;
     const F d = dcur;
-    fail = (fail < 0 && !(d > F(0))) ? j : fail;
     const F w = row[j];
     d_mine = (lane == j) ? d : d_mine;
     const F q = w * dinv;
@@ -306,7 +310,7 @@ __device__ __forceinline__ void sweep_half(F (&row)[T], int j0, F& dcur, F& d_mi
       dcur = fma(-(wn * wn), dinv, p);
       dinv_next = recip(dcur);
     }
-    row[j] = (lane == j) ? F(1) : q;
+    row[j] = q;   // lane j: d_j * (1 / d_j), 1 up to the reciprocal's last bit
     F wl[H];
 #pragma unroll
     for (int l = j + 1; l < j0 + H; ++l) wl[l - j0] = readlane(w, l);
@@ -361,6 +365,10 @@ __device__ __forceinline__ int sweep_ldlt(F (&row)[T], lds_t<F>* sq, lds_t<F>* s
   // column c scaled by sqrt(d_c): the roots broadcast through LDS (lane c
   // writes its own; within one wave LDS accesses complete in order), which
   // keeps 2T lane reads off the vector ALU
+  {
+    const unsigned long long bad = __ballot(lane < T && !(d_mine > F(0)));
+    fail = bad ? (int)__builtin_ctzll(bad) : -1;
+  }
   if (lane < T) sd[lane] = prec_sqrt(d_mine);
 #pragma unroll
   for (int c = 0; c < T; ++c) row[c] *= sd[c];
