@@ -107,19 +107,46 @@ __device__ __forceinline__ int tidx(const Args<F>& A, int64_t R, int64_t C) { re
 
 // ---------------------------------------------------------------- block I/O with atomics
 
-// Block (bi, bj) of tile (R, C) in accumulator form (see common.h).  On a
-// diagonal tile the positions past row n-1 get an identity.
+// A dense T x T tile in column-major workspace memory, in accumulator form.
 template <typename F>
-__device__ __forceinline__ v4_t<F> ablk_load(const BandT<F>& a, int64_t R, int64_t C, int bi, int bj) {
-  const RunT<F> run = acc_run(a, R, C, bi, bj);
-  v4_t<F> acc;
+__device__ __forceinline__ int wblk_index(int bi, int bj, int r) {
+  const int lane = lane_id();
+  return (16 * bj + Prec<F>::acc_col0(lane) + Prec<F>::ACC_STEP * r) * T + 16 * bi + (lane & 15);
+}
+template <typename F>
+__device__ __forceinline__ void wblk_store(glb_t<F>* t, int bi, int bj, v4_t<F> v) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) astore<F>(t + wblk_index<F>(bi, bj, r), v[r]);
+}
+
+// Block (bi, bj) of tile (R, C) in accumulator form, from `pre` (a dense tile
+// in workspace, accumulator order) when not null, else from the band.  The
+// four loads are issued unconditionally (positions outside the band read the
+// zero word), so that the loads of several blocks stay in flight together: a
+// branch around a load, or a use of a value right after its load, makes the
+// wave wait for every load still in flight.  On a diagonal tile the positions
+// past row n-1 take an identity, applied by blk_ident once a group's loads
+// have all been issued.
+template <typename F>
+__device__ __forceinline__ v4_t<F> blk_issue(const Args<F>& A, const glb_t<F>* pre, int64_t R, int64_t C, int bi,
+                                             int bj) {
+  const RunT<F> run = acc_run(A.a, R, C, bi, bj);
+  v4_t<F> v;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    F v = run.ald(r);
-    if (R == C && !run.row_ok && run.d0 - run.ds * r == 0) v = F(1);
-    acc[r] = v;
+    const glb_t<F>* p = pre ? pre + wblk_index<F>(bi, bj, r) : (run.in(r) ? run.at(r) : A.w.zero);
+    v[r] = aload<F>(opaque_ptr(p));
   }
-  return acc;
+  return v;
+}
+
+template <typename F>
+__device__ __forceinline__ void blk_ident(const BandT<F>& a, int64_t R, int64_t C, int bi, int bj, v4_t<F>& v) {
+  if (R != C) return;
+  const RunT<F> run = acc_run(a, R, C, bi, bj);
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    if (!run.row_ok && run.d0 - run.ds * r == 0) v[r] = F(1);
 }
 
 template <typename F>
@@ -128,25 +155,6 @@ __device__ __forceinline__ void ablk_store(const BandT<F>& a, int64_t R, int64_t
 #pragma unroll
   for (int r = 0; r < 4; ++r)
     if (run.in(r)) astore(run.at(r), v[r]);
-}
-
-// A dense T x T tile in column-major workspace memory, in accumulator form.
-template <typename F>
-__device__ __forceinline__ int wblk_index(int bi, int bj, int r) {
-  const int lane = lane_id();
-  return (16 * bj + Prec<F>::acc_col0(lane) + Prec<F>::ACC_STEP * r) * T + 16 * bi + (lane & 15);
-}
-template <typename F>
-__device__ __forceinline__ v4_t<F> wblk_load(const glb_t<F>* t, int bi, int bj) {
-  v4_t<F> v;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) v[r] = aload<F>(t + wblk_index<F>(bi, bj, r));
-  return v;
-}
-template <typename F>
-__device__ __forceinline__ void wblk_store(glb_t<F>* t, int bi, int bj, v4_t<F> v) {
-#pragma unroll
-  for (int r = 0; r < 4; ++r) astore<F>(t + wblk_index<F>(bi, bj, r), v[r]);
 }
 
 // acc -= X_blk(bi) Y_blk(bj)^T with X = tile (Rx, s), Y = tile (Ry, s) from the band.
@@ -251,7 +259,7 @@ __device__ __attribute__((noinline)) void task_off(const Args<F>& A_, int64_t R,
   const Args<F> A = A_;
   const int wave = wave_id();
   const int bi = wave & 1, bj = wave >> 1;
-  v4_t<F> acc = ablk_load(A.a, R, C, bi, bj);
+  v4_t<F> acc = blk_issue<F>(A, nullptr, R, C, bi, bj);
   const int64_t s0 = R - A.K > 0 ? R - A.K : 0;
   int ok = apply_terms(A, R, C, s0, C, bi, bj, acc) ? 1 : 0;
   if (ok) ok = wave_wait(&A.w.tflag[tidx(A, C, C)], A.w) ? 1 : 0;
@@ -325,8 +333,8 @@ __device__ __attribute__((noinline)) void task_off2(const Args<F>& A_, int64_t R
   const Args<F> A = A_;
   const int wave = wave_id();
   const int bi = wave & 1, bj = wave >> 1;
-  v4_t<F> acc0 = ablk_load(A.a, R, C, bi, bj);
-  v4_t<F> acc1 = ablk_load(A.a, R + 1, C, bi, bj);
+  v4_t<F> acc0 = blk_issue<F>(A, nullptr, R, C, bi, bj);
+  v4_t<F> acc1 = blk_issue<F>(A, nullptr, R + 1, C, bi, bj);
   const int64_t s0 = R - A.K > 0 ? R - A.K : 0;
   int ok = apply_terms2(A, R, C, s0, C, bi, bj, acc0, acc1) ? 1 : 0;
   if (ok) ok = wave_wait(&A.w.tflag[tidx(A, C, C)], A.w) ? 1 : 0;
@@ -386,8 +394,9 @@ __device__ __attribute__((noinline)) void task_pre(const Args<F>& A_, int64_t m,
   glb_t<F>* pd = po + T * T;
   const int bi = wave & 1, bj = wave >> 1;
   const int di = (wave >= 2), dj = (wave == 3);
-  v4_t<F> acc = ablk_load(A.a, m, m - 1, bi, bj);
-  v4_t<F> accd = ablk_load(A.a, m, m, di, dj);
+  v4_t<F> acc = blk_issue<F>(A, nullptr, m, m - 1, bi, bj);
+  v4_t<F> accd = blk_issue<F>(A, nullptr, m, m, di, dj);
+  blk_ident(A.a, m, m, di, dj, accd);
   int ok = 1;
   int64_t s = s0;
   while (s < s1) {
@@ -436,7 +445,7 @@ __device__ __attribute__((noinline)) void task_p(const Args<F>& A_, int64_t m, l
   const Args<F> A = A_;
   const int wave = wave_id();
   const int bi = wave & 1, bj = wave >> 1;
-  v4_t<F> acc = ablk_load(A.a, m, m - 2, bi, bj);
+  v4_t<F> acc = blk_issue<F>(A, nullptr, m, m - 2, bi, bj);
   const int64_t s0 = m - A.K > 0 ? m - A.K : 0;
   const int ok = apply_terms(A, m, m - 2, s0, m - 4, bi, bj, acc) ? 1 : 0;
   wblk_store(A.w.pre + (m - 1) * 3 * T * T + 2 * T * T, bi, bj, acc);
@@ -464,29 +473,41 @@ struct SpineLds {
   lds_t<F>* l2prev;      // L(C, C-2)
 };
 
+// An inverse from LDS (row-major, pitch LP) to the workspace, column-major:
+// store p covers elements 64p .. 64p+63.  Not waited for.
+template <typename F>
+__device__ __forceinline__ void store_linvt(const lds_t<F>* linvt, glb_t<F>* dst) {
+  const int lane = lane_id();
+  const int r = lane & 31, h = lane >> 5;
+  F v[T / 2];
+#pragma unroll
+  for (int p = 0; p < T / 2; ++p) v[p] = linvt[r * LP + 2 * p + h];  // element (r, 2p + h)
+#pragma unroll
+  for (int p = 0; p < T / 2; ++p) astore(dst + 64 * p + lane, v[p]);
+}
+
 // Wave 0: the sweep of the staged diagonal tile D(C); L(C,C) replaces the
 // tile in its LDS buffer (column-major, pitch LP) and L(C,C)^{-T} goes to
-// `linvt` (row-major, pitch LP).  On entry the previous step's inverse,
-// `linvt_prev`, is copied to `lt_prev` (column-major: store p covers elements
-// 64p .. 64p+63), and between the two halves of the sweep, once those stores
-// have long completed, `flag_prev` is raised: the helpers' trsm takes
-// L(C-1,C-1)^{-T} from there.
+// `linvt` (row-major, pitch LP).  With `flag_prev` (the FP32 schedule), the
+// previous step's inverse, `linvt_prev`, is first copied to `lt_prev`, and
+// between the two halves of the sweep, once those stores have long
+// completed, `flag_prev` is raised: the helpers' trsm takes L(C-1,C-1)^{-T}
+// from there.  (The FP64 schedule stores the inverse right after the sweep,
+// from wave 0, which is free then, and `flag_stored` is raised here, at the
+// start of the next sweep, once those stores have drained.)
 template <typename F>
 __device__ __forceinline__ void spine_sweep(lds_t<F>* diag, lds_t<F>* sd, lds_t<F>* linvt, const lds_t<F>* linvt_prev,
-                                            glb_t<F>* lt_prev, glb_i* flag_prev, int64_t C, int64_t n,
+                                            glb_t<F>* lt_prev, glb_i* flag_prev, glb_i* flag_stored, int64_t C, int64_t n,
                                             unsigned long long* first_fail, glb_i* abort_flag, lds_i* s_fail) {
   const int lane = lane_id();
-  if (flag_prev) {
-    const int r = lane & 31, h = lane >> 5;
-    F v[T / 2];
-#pragma unroll
-    for (int p = 0; p < T / 2; ++p) v[p] = linvt_prev[r * LP + 2 * p + h];  // element (r, 2p + h)
-#pragma unroll
-    for (int p = 0; p < T / 2; ++p) astore(lt_prev + 64 * p + lane, v[p]);
-  }
+  if (flag_prev) store_linvt(linvt_prev, lt_prev);
   F row[T];
 #pragma unroll
   for (int c = 0; c < T; ++c) row[c] = lane < T ? diag[c * LP + lane] : ((lane - T) == c ? F(1) : F(0));
+  if (flag_stored) {
+    wait_vmem();
+    if (lane == 0) raise_flag(flag_stored);
+  }
   auto mid = [flag_prev, lane]() {
     if (flag_prev) {
       wait_vmem();
@@ -599,11 +620,29 @@ __device__ __forceinline__ bool lds_wait(lds_i* f, int v) {
   return true;
 }
 
+// The flags of L(C, C-1) and L(C, C-2), raised by the last of waves 1-3 to
+// count in once its own stores of them have drained.  In the FP64 schedule
+// all those stores were issued in the previous step (L(C, C-2) in its phase A,
+// L(C, C-1) in its phase BC), and this runs at the start of phase A, where
+// the wait costs little; in the FP32 one wave 1 stores a block of L(C, C-1)
+// during phase A, and this runs at its end.
+template <typename F>
+__device__ __forceinline__ void publish_prev(const Args<F>& A, int64_t C, lds_i* s_pub) {
+  wait_vmem();
+  if (C >= 1 && lane_id() == 0) {
+    const int before = __hip_atomic_fetch_add(s_pub, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (before == 3 * (int)C - 1) {
+      if (A.K >= 1) raise_flag(&A.w.tflag[tidx(A, C, C - 1)]);
+      if (A.K >= 2 && C >= 2) raise_flag(&A.w.tflag[tidx(A, C, C - 2)]);
+    }
+  }
+}
+
 // Waves 1-3 in phase A of step C (m = C+1), alongside the sweep:
-//   * publication of the previous step: wave 1 stores wave 0's block of
+//   * publication of the previous step (publish_prev): at the start (FP64),
+//     or (FP32) at the end, after wave 1 has stored wave 0's block of
 //     L(C, C-1) from LDS (after its own loads, which would otherwise wait for
-//     that store); at the end each wave drains its stores and counts in, and
-//     the third raises the flags of L(C, C-1) and L(C, C-2);
+//     that store);
 //   * tile (m, C-1): the helpers' sum over s <= C-4, here the terms s = C-3
 //     and C-2 (operands L(C-1, C-3) and L(C-1, C-2) still in LDS), then
 //     L(m, C-1) = tile L(C-1,C-1)^{-T} (the previous sweep's inverse, also
@@ -618,7 +657,10 @@ __device__ __forceinline__ void spine_prepare(const Args<F>& A, int64_t C, const
   const int lane = lane_id();
   const int K = A.K;
   const int64_t m = C + 1;
-  const bool copy0 = C >= 1 && K >= 1;  // wave 1 stores wave 0's block of L(C, C-1)
+  // FP32 schedule: wave 1 stores wave 0's block of L(C, C-1) (in the FP64 one
+  // waves 1 and 3 store all of L(C, C-1) after the previous sweep)
+  const bool copy0 = !acc_is_operand<F>() && C >= 1 && K >= 1;
+  if constexpr (acc_is_operand<F>()) publish_prev(A, C, s_pub);
   if (next) {
     const bool pre_o = K >= 4 && m >= 4;  // (m, C), (m, m) from H(m)
     const bool pre_p = K >= 5 && C >= 4;  // (m, C-1) from P(m)
@@ -642,12 +684,17 @@ __device__ __forceinline__ void spine_prepare(const Args<F>& A, int64_t C, const
 #pragma unroll
       for (int b = 0; b < 7; ++b) {
         const int bi = b < 4 ? (b & 1) : (b >= 5), bj = b < 4 ? (b >> 1) : (b == 6);
-        if (pre_o) acc[b] = wblk_load(po + (b < 4 ? 0 : T * T), bi, bj);
-        else acc[b] = ablk_load(A.a, m, b < 4 ? C : m, bi, bj);
+        acc[b] = blk_issue<F>(A, pre_o ? po + (b < 4 ? 0 : T * T) : nullptr, m, b < 4 ? C : m, bi, bj);
       }
       if (t2) {
         term_load_x(A, m, C - 2, 0, x3[0]);
         term_load_x(A, m, C - 2, 1, x3[1]);
+      }
+      if (!pre_o) {
+#pragma unroll
+        for (int b = 4; b < 7; ++b) blk_ident(A.a, m, m, b >= 5, b == 6, acc[b]);
+      }
+      if (t2) {
 #pragma unroll
         for (int b = 0; b < 7; ++b) {
           const int bi = b < 4 ? (b & 1) : (b >= 5), bj = b < 4 ? (b >> 1) : (b == 6);
@@ -681,7 +728,7 @@ __device__ __forceinline__ void spine_prepare(const Args<F>& A, int64_t C, const
         F x3[T / 4], x4[T / 4], y1[2][T / 4], y2[2][T / 4];
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj)
-          pp[bj] = pre_p ? wblk_load(A.w.pre + C * 3 * T * T + 2 * T * T, h, bj) : ablk_load(A.a, m, C - 1, h, bj);
+          pp[bj] = blk_issue<F>(A, pre_p ? A.w.pre + C * 3 * T * T + 2 * T * T : nullptr, m, C - 1, h, bj);
         if (t2) term_load_x(A, m, C - 2, h, x3);
         if (t3) term_load_x(A, m, C - 3, h, x4);
         // L(C-1, C-2) and L(C-1, C-3), computed by the spine two steps ago,
@@ -766,14 +813,7 @@ __device__ __forceinline__ void spine_prepare(const Args<F>& A, int64_t C, const
   } else if (wave == 1 && copy0) {
     ablk_store(A.a, C, C - 1, 0, 0, blk_from_lds<F>(S.lprev, 0, 0));
   }
-  wait_vmem();
-  if (C >= 1 && lane == 0) {
-    const int before = __hip_atomic_fetch_add(s_pub, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    if (before == 3 * (int)C - 1) {
-      if (K >= 1) raise_flag(&A.w.tflag[tidx(A, C, C - 1)]);
-      if (K >= 2 && C >= 2) raise_flag(&A.w.tflag[tidx(A, C, C - 2)]);
-    }
-  }
+  if constexpr (!acc_is_operand<F>()) publish_prev(A, C, s_pub);
   // the next step's flags, read now and used then (a load in flight meanwhile)
   early = 1;
   if (C + 2 < A.NB && lane < 4) {
@@ -799,8 +839,9 @@ __device__ __attribute__((noinline)) void spine_wave0(const Args<F>& A_, const S
     const unsigned long long t0 = stamp(prof);
     // phase A
     spine_sweep<F>(S.diag, S.sd, S.linvt, S.linvt_prev, A.w.linvt + (C - 1) * T * T,
-                   C >= 1 ? &A.w.tflag[tidx(A, C - 1, C - 1)] : nullptr, C, a.n, A.w.first_fail, A.w.abort_flag,
-                   s_fail);
+                   !acc_is_operand<F>() && C >= 1 ? &A.w.tflag[tidx(A, C - 1, C - 1)] : nullptr,
+                   acc_is_operand<F>() && C >= 1 ? &A.w.tflag[tidx(A, C - 1, C - 1)] : nullptr, C, a.n,
+                   A.w.first_fail, A.w.abort_flag, s_fail);
     const unsigned long long t1 = stamp(prof);
     lds_barrier();
     const unsigned long long t2 = stamp(prof);
@@ -811,24 +852,44 @@ __device__ __attribute__((noinline)) void spine_wave0(const Args<F>& A_, const S
       }
       return;
     }
-    // phase B: block (0, 0) of L(C+1, C) = acco * L(C,C)^{-T}; wave 1 stores it
-    // during the next step
-    if (A.K >= 1) blk_to_lds(S.lcur, 0, 0, blk_trsm_lds(S.acco, S.linvt, 0, 0, LP));
-    lds_barrier();
-    const unsigned long long t3 = stamp(prof);
-    // phase C: block (0, 0) of the next diagonal tile, staged in acco's buffer
-    v4_t<F> acc = blk_from_lds<F>(S.accd, 0, 0);
-    if (A.K >= 1) acc = blk_gemm_lds<F>(S.lcur, S.lcur, 0, 0, acc);
-    blk_to_lds<F>(S.acco, 0, 0, acc);
-    blk_to_lds<F>(S.acco, 0, 1, v4_t<F>{0, 0, 0, 0});
-    lds_t<F>* t = S.diag; S.diag = S.acco; S.acco = t;
-    t = S.lprev; S.lprev = S.lcur; S.lcur = t;
-    t = S.l2prev; S.l2prev = S.l2cur; S.l2cur = t;
-    t = S.linvt_prev; S.linvt_prev = S.linvt; S.linvt = t;
-    lds_barrier();
-    if (prof) {
-      const unsigned long long t4 = stamp(true);
-      p_sweep += t1 - t0, p_wait += t2 - t1, p_b += t3 - t2, p_c += t4 - t3, steps += 1;
+    if constexpr (acc_is_operand<F>()) {
+      // phase BC (waves 1-3 finish L(C+1, C) and the next diagonal tile):
+      // store L(C,C)^{-T} for the helpers' trsm (its flag is raised at the
+      // start of the next sweep, once the stores have drained) and L(C,C), and
+      // zero the upper block of the next diagonal tile (staged in accd's buffer)
+      store_linvt(S.linvt, A.w.linvt + C * T * T);
+      blk_to_lds<F>(S.accd, 0, 1, v4_t<F>{0, 0, 0, 0});
+      store_lcc(S.diag, C, a);
+      const unsigned long long t3 = stamp(prof);
+      lds_t<F>* t = S.diag; S.diag = S.accd; S.accd = t;
+      t = S.lprev; S.lprev = S.lcur; S.lcur = t;
+      t = S.l2prev; S.l2prev = S.l2cur; S.l2cur = t;
+      t = S.linvt_prev; S.linvt_prev = S.linvt; S.linvt = t;
+      lds_barrier();
+      if (prof) {
+        const unsigned long long t4 = stamp(true);
+        p_sweep += t1 - t0, p_wait += t2 - t1, p_b += t3 - t2, p_c += t4 - t3, steps += 1;
+      }
+    } else {
+      // phase B: block (0, 0) of L(C+1, C) = acco * L(C,C)^{-T}; wave 1 stores it
+      // during the next step
+      if (A.K >= 1) blk_to_lds(S.lcur, 0, 0, blk_trsm_lds(S.acco, S.linvt, 0, 0, LP));
+      lds_barrier();
+      const unsigned long long t3 = stamp(prof);
+      // phase C: block (0, 0) of the next diagonal tile, staged in acco's buffer
+      v4_t<F> acc = blk_from_lds<F>(S.accd, 0, 0);
+      if (A.K >= 1) acc = blk_gemm_lds<F>(S.lcur, S.lcur, 0, 0, acc);
+      blk_to_lds<F>(S.acco, 0, 0, acc);
+      blk_to_lds<F>(S.acco, 0, 1, v4_t<F>{0, 0, 0, 0});
+      lds_t<F>* t = S.diag; S.diag = S.acco; S.acco = t;
+      t = S.lprev; S.lprev = S.lcur; S.lcur = t;
+      t = S.l2prev; S.l2prev = S.l2cur; S.l2cur = t;
+      t = S.linvt_prev; S.linvt_prev = S.linvt; S.linvt = t;
+      lds_barrier();
+      if (prof) {
+        const unsigned long long t4 = stamp(true);
+        p_sweep += t1 - t0, p_wait += t2 - t1, p_b += t3 - t2, p_c += t4 - t3, steps += 1;
+      }
     }
   }
 }
@@ -859,30 +920,68 @@ __device__ __attribute__((noinline)) void spine_waves123(const Args<F>& A_, cons
       if (wave == 1) store_lcc(S.diag, C, a);
       return;
     }
-    // phase B: L(C+1, C) = acco * L(C,C)^{-T}, one block per wave, stored now
-    if (A.K >= 1) {
-      const int bi = wave & 1, bj = wave >> 1;
-      const v4_t<F> v = blk_trsm_lds(S.acco, S.linvt, bi, bj, LP);
-      blk_to_lds(S.lcur, bi, bj, v);
-      ablk_store(a, C + 1, C, bi, bj, v);
-    }
-    lds_barrier();
-    // phase C: blocks (1,0), (1,1) of the next diagonal tile on waves 2, 3,
-    // staged in acco's buffer; wave 1 stores L(C,C), which stays in the
-    // diagonal tile's buffer until the rotation
-    if (wave >= 2) {
-      const int bi = 1, bj = (wave == 3);
-      v4_t<F> acc = blk_from_lds<F>(S.accd, bi, bj);
-      if (A.K >= 1) acc = blk_gemm_lds<F>(S.lcur, S.lcur, bi, bj, acc);
-      blk_to_lds<F>(S.acco, bi, bj, acc);
+    if constexpr (acc_is_operand<F>()) {
+      // phase BC: wave w takes block (ci, cj) of the next diagonal tile,
+      // (0,0), (1,0), (1,1) for waves 1, 2, 3, and computes the row blocks of
+      // L(C+1, C) = acco * L(C,C)^{-T} that its last term needs (wave 2 both,
+      // the others their own); their accumulators are the operands of that
+      // term, so no barrier separates the trsm from it.  Waves 1 and 3 store
+      // their row block and stage it for the next step.  The new tile goes
+      // to accd's buffer, each wave over the block it read.
+      const int ci = wave >= 2, cj = wave == 3;
+      v4_t<F> acc = blk_from_lds<F>(S.accd, ci, cj);
+      if (A.K >= 1) {
+        v4_t<F> oi[2], oj[2];
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) oi[kb] = blk_trsm_lds(S.acco, S.linvt, ci, kb, LP);
+        if (wave == 2) {
+#pragma unroll
+          for (int kb = 0; kb < 2; ++kb) oj[kb] = blk_trsm_lds(S.acco, S.linvt, 0, kb, LP);
+        } else {
+#pragma unroll
+          for (int kb = 0; kb < 2; ++kb) {
+            oj[kb] = oi[kb];
+            blk_to_lds(S.lcur, ci, kb, oi[kb]);
+            ablk_store(a, C + 1, C, ci, kb, oi[kb]);
+          }
+        }
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc = mfma_xyt(-oi[kb][r], oj[kb][r], acc);
+      }
+      blk_to_lds<F>(S.accd, ci, cj, acc);
+      lds_t<F>* t = S.diag; S.diag = S.accd; S.accd = t;
+      t = S.lprev; S.lprev = S.lcur; S.lcur = t;
+      t = S.l2prev; S.l2prev = S.l2cur; S.l2cur = t;
+      t = S.linvt_prev; S.linvt_prev = S.linvt; S.linvt = t;
+      lds_barrier();
     } else {
-      store_lcc(S.diag, C, a);
+      // phase B: L(C+1, C) = acco * L(C,C)^{-T}, one block per wave, stored now
+      if (A.K >= 1) {
+        const int bi = wave & 1, bj = wave >> 1;
+        const v4_t<F> v = blk_trsm_lds(S.acco, S.linvt, bi, bj, LP);
+        blk_to_lds(S.lcur, bi, bj, v);
+        ablk_store(a, C + 1, C, bi, bj, v);
+      }
+      lds_barrier();
+      // phase C: blocks (1,0), (1,1) of the next diagonal tile on waves 2, 3,
+      // staged in acco's buffer; wave 1 stores L(C,C), which stays in the
+      // diagonal tile's buffer until the rotation
+      if (wave >= 2) {
+        const int bi = 1, bj = (wave == 3);
+        v4_t<F> acc = blk_from_lds<F>(S.accd, bi, bj);
+        if (A.K >= 1) acc = blk_gemm_lds<F>(S.lcur, S.lcur, bi, bj, acc);
+        blk_to_lds<F>(S.acco, bi, bj, acc);
+      } else {
+        store_lcc(S.diag, C, a);
+      }
+      lds_t<F>* t = S.diag; S.diag = S.acco; S.acco = t;
+      t = S.lprev; S.lprev = S.lcur; S.lcur = t;
+      t = S.l2prev; S.l2prev = S.l2cur; S.l2cur = t;
+      t = S.linvt_prev; S.linvt_prev = S.linvt; S.linvt = t;
+      lds_barrier();
     }
-    lds_t<F>* t = S.diag; S.diag = S.acco; S.acco = t;
-    t = S.lprev; S.lprev = S.lcur; S.lcur = t;
-    t = S.l2prev; S.l2prev = S.l2cur; S.l2cur = t;
-    t = S.linvt_prev; S.linvt_prev = S.linvt; S.linvt = t;
-    lds_barrier();
   }
 }
 
@@ -909,7 +1008,9 @@ __device__ void spine(const Args<F>& A, lds_t<F>* base, lds_i* s_fail, lds_i* s_
   // stage tile (0,0)
   if (wave >= 1) {
     const int bi = (wave >= 2), bj = (wave == 3);
-    blk_to_lds(S.diag, bi, bj, ablk_load(A.a, 0, 0, bi, bj));
+    v4_t<F> v = blk_issue<F>(A, nullptr, 0, 0, bi, bj);
+    blk_ident(A.a, 0, 0, bi, bj, v);
+    blk_to_lds(S.diag, bi, bj, v);
   } else {
     blk_to_lds(S.diag, 0, 1, v4_t<F>{0, 0, 0, 0});
   }
