@@ -72,6 +72,38 @@ struct Args {
   Ws<F> w;
 };
 
+// The same value in every lane, in scalar registers.  Arguments of a
+// non-inlined function (and structures read through a reference) arrive in
+// vector registers; without this every branch on them would be a masked one
+// and every address computed from them vector arithmetic.
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ unsigned uni(unsigned x) { return (unsigned)__builtin_amdgcn_readfirstlane((int)x); }
+__device__ __forceinline__ int64_t uni(int64_t x) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(uint64_t)x);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+template <typename P>
+__device__ __forceinline__ P* uni(P* p) {
+  return (P*)(uintptr_t)uni((int64_t)(uintptr_t)p);
+}
+template <typename P>
+__device__ __forceinline__ __attribute__((address_space(3))) P* uni_lds(__attribute__((address_space(3))) P* p) {
+  return (__attribute__((address_space(3))) P*)(uintptr_t)(unsigned)uni((int)(unsigned)(uintptr_t)p);
+}
+
+template <typename F>
+__device__ __forceinline__ Args<F> uniform(const Args<F>& A_) {
+  Args<F> A;
+  A.a.ab = uni(A_.a.ab), A.a.n = uni(A_.a.n), A.a.k = uni(A_.a.k), A.a.ldab = uni(A_.a.ldab);
+  A.NB = uni(A_.NB), A.K = uni(A_.K), A.ntickets = uni(A_.ntickets), A.spare_spine_cu = uni(A_.spare_spine_cu);
+  A.w.tflag = uni(A_.w.tflag), A.w.hflag = uni(A_.w.hflag), A.w.pflag = uni(A_.w.pflag);
+  A.w.linvt = uni(A_.w.linvt), A.w.pre = uni(A_.w.pre), A.w.queue = uni(A_.w.queue);
+  A.w.abort_flag = uni(A_.w.abort_flag), A.w.first_fail = uni(A_.w.first_fail), A.w.spine_cu = uni(A_.w.spine_cu);
+  A.w.zero = uni(A_.w.zero), A.w.prof = uni(A_.w.prof);
+  return A;
+}
+
 __device__ __forceinline__ int aflag(const glb_i* p) {
   return __builtin_amdgcn_readfirstlane(__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
 }
@@ -256,7 +288,7 @@ __device__ __forceinline__ v4_t<F> trsm_from_lds(const lds_t<F>* x, const glb_t<
 template <typename F>
 __device__ __attribute__((noinline)) void task_off(const Args<F>& A_, int64_t R, int64_t C, lds_t<F>* stage,
                                                    lds_i* s_ok) {
-  const Args<F> A = A_;
+  const Args<F> A = uniform(A_);
   const int wave = wave_id();
   const int bi = wave & 1, bj = wave >> 1;
   v4_t<F> acc = blk_issue<F>(A, nullptr, R, C, bi, bj);
@@ -330,7 +362,7 @@ __device__ __forceinline__ bool apply_terms2(const Args<F>& A, int64_t R, int64_
 template <typename F>
 __device__ __attribute__((noinline)) void task_off2(const Args<F>& A_, int64_t R, int64_t C, lds_t<F>* stage,
                                                     lds_i* s_ok) {
-  const Args<F> A = A_;
+  const Args<F> A = uniform(A_);
   const int wave = wave_id();
   const int bi = wave & 1, bj = wave >> 1;
   v4_t<F> acc0 = blk_issue<F>(A, nullptr, R, C, bi, bj);
@@ -385,7 +417,7 @@ __device__ __forceinline__ void pre_apply(const PreOps<F>& o, bool bi, bool di, 
 
 template <typename F>
 __device__ __attribute__((noinline)) void task_pre(const Args<F>& A_, int64_t m, lds_i* s_ok) {
-  const Args<F> A = A_;
+  const Args<F> A = uniform(A_);
   const int wave = wave_id();
   const int lane = lane_id();
   const int64_t s0 = m - A.K > 0 ? m - A.K : 0;
@@ -442,7 +474,7 @@ __device__ __attribute__((noinline)) void task_pre(const Args<F>& A_, int64_t m,
 // terms s <= m-5, into the workspace slot of row m-1.
 template <typename F>
 __device__ __attribute__((noinline)) void task_p(const Args<F>& A_, int64_t m, lds_i* s_ok) {
-  const Args<F> A = A_;
+  const Args<F> A = uniform(A_);
   const int wave = wave_id();
   const int bi = wave & 1, bj = wave >> 1;
   v4_t<F> acc = blk_issue<F>(A, nullptr, m, m - 2, bi, bj);
@@ -472,6 +504,15 @@ struct SpineLds {
   lds_t<F>* l2cur;       // L(C+1, C-1); in phase A first L(C-1, C-3) (two steps old)
   lds_t<F>* l2prev;      // L(C, C-2)
 };
+
+template <typename F>
+__device__ __forceinline__ SpineLds<F> uniform(const SpineLds<F>& S_) {
+  SpineLds<F> S;
+  S.diag = uni_lds(S_.diag), S.sd = uni_lds(S_.sd), S.linvt = uni_lds(S_.linvt);
+  S.linvt_prev = uni_lds(S_.linvt_prev), S.acco = uni_lds(S_.acco), S.accd = uni_lds(S_.accd);
+  S.lcur = uni_lds(S_.lcur), S.lprev = uni_lds(S_.lprev), S.l2cur = uni_lds(S_.l2cur), S.l2prev = uni_lds(S_.l2prev);
+  return S;
+}
 
 // An inverse from LDS (row-major, pitch LP) to the workspace, column-major:
 // store p covers elements 64p .. 64p+63.  Not waited for.
@@ -829,6 +870,8 @@ __device__ __forceinline__ void spine_prepare(const Args<F>& A, int64_t C, const
 // pass the same three barriers per step.
 template <typename F>
 __device__ __attribute__((noinline)) void spine_wave0(const Args<F>& A_, const SpineLds<F>& S_, lds_i* s_fail) {
+  // (left in vector registers: the sweep needs the scalar registers for its
+  // lane reads)
   const Args<F> A = A_;
   SpineLds<F> S = S_;
   const BandT<F>& a = A.a;
@@ -897,8 +940,8 @@ __device__ __attribute__((noinline)) void spine_wave0(const Args<F>& A_, const S
 template <typename F>
 __device__ __attribute__((noinline)) void spine_waves123(const Args<F>& A_, const SpineLds<F>& S_, lds_i* sync,
                                                          lds_i* s_pub, lds_i* s_fail) {
-  const Args<F> A = A_;
-  SpineLds<F> S = S_;
+  const Args<F> A = uniform(A_);
+  SpineLds<F> S = uniform(S_);
   const BandT<F>& a = A.a;
   const int wave = wave_id();
   int early = 0;
