@@ -5,13 +5,17 @@
 // the spine (whoever takes ticket 0), carries the dependency chain along the
 // diagonal and the first two sub-diagonals, one tile column per step C:
 //   phase A  wave 0: factor the staged diagonal tile (register sweep) ->
-//            L(C,C) and L(C,C)^{-T} in LDS (to global memory during phase C
-//            and the next sweep);
+//            L(C,C) and L(C,C)^{-T} in LDS;
 //            waves 1-3: L(C+1, C-1) from its pre-accumulated sum, the terms
-//            s = C-3, C-2 and the previous step's L(C-1,C-1)^{-T}; then tile
-//            (C+1, C) and the next diagonal tile with the terms s = C-2, C-1;
-//   phase B  all waves: L(C+1, C) = tile * L(C,C)^{-T};
-//   phase C  waves 0, 2, 3: next diagonal tile -= L(C+1,C) L(C+1,C)^T, staged.
+//            the helpers leave and the previous step's L(C-1,C-1)^{-T}; then
+//            tile (C+1, C) and the next diagonal tile with the terms s = C-2,
+//            C-1;
+//   FP64, phase BC: waves 1-3 compute the row blocks of L(C+1, C) = tile *
+//            L(C,C)^{-T} that their block of the next diagonal tile needs and
+//            subtract L(C+1,C) L(C+1,C)^T from it; wave 0 stores L(C,C) and
+//            L(C,C)^{-T};
+//   FP32, phase B: all waves: L(C+1, C) = tile * L(C,C)^{-T};
+//         phase C: waves 0, 2, 3: next diagonal tile -= L(C+1,C) L(C+1,C)^T.
 // Helper workgroups take the other tickets, in an order where every task only
 // waits for lower tickets or for spine steps:
 //   O(R, C), R - C >= 3: acc = A(R,C) - sum_s L(R,s) L(C,s)^T (terms applied as
@@ -20,7 +24,7 @@
 //   H(m):    the tiles (m, m-1) and (m, m) the spine completes at step m-1,
 //            summed over s <= m-4;
 //   P(m):    the tile (m, m-2) the spine completes at step m-1, summed over
-//            s <= m-5.
+//            s <= m-4.
 // Whatever the spine takes from a helper depends only on spine results at
 // least two steps old, so the helpers' round trips stay off its chain.
 // Data between workgroups moves through relaxed agent-scope atomic loads and
@@ -471,7 +475,9 @@ __device__ __attribute__((noinline)) void task_pre(const Args<F>& A_, int64_t m,
 }
 
 // P(m): the tile (m, m-2) the spine completes at step m-1, summed over the
-// terms s <= m-5, into the workspace slot of row m-1.
+// terms s <= m-4, into the workspace slot of row m-1.  Its last term uses
+// L(m, m-4), a tile of the first pair of column m-4, and L(m-2, m-4), which
+// the spine publishes at the start of step m-2: one step before it is needed.
 template <typename F>
 __device__ __attribute__((noinline)) void task_p(const Args<F>& A_, int64_t m, lds_i* s_ok) {
   const Args<F> A = uniform(A_);
@@ -479,7 +485,7 @@ __device__ __attribute__((noinline)) void task_p(const Args<F>& A_, int64_t m, l
   const int bi = wave & 1, bj = wave >> 1;
   v4_t<F> acc = blk_issue<F>(A, nullptr, m, m - 2, bi, bj);
   const int64_t s0 = m - A.K > 0 ? m - A.K : 0;
-  const int ok = apply_terms(A, m, m - 2, s0, m - 4, bi, bj, acc) ? 1 : 0;
+  const int ok = apply_terms(A, m, m - 2, s0, m - 3, bi, bj, acc) ? 1 : 0;
   wblk_store(A.w.pre + (m - 1) * 3 * T * T + 2 * T * T, bi, bj, acc);
   if (!ok && lane_id() == 0) *s_ok = 0;
   wait_vmem();
@@ -637,9 +643,9 @@ __device__ __forceinline__ StepFlags<F> step_flags(const Args<F>& A, int64_t C) 
   const int64_t m = C + 1;
   StepFlags<F> r;
   r.f[0] = K >= 4 && m >= 4 ? &A.w.hflag[m] : nullptr;                // H(m)
-  r.f[1] = K >= 5 && C >= 4 ? &A.w.pflag[m] : nullptr;                // P(m)
+  r.f[1] = K >= 4 && m >= 4 ? &A.w.pflag[m] : nullptr;                // P(m)
   r.f[2] = K >= 3 && C >= 2 ? &A.w.tflag[tidx(A, m, C - 2)] : nullptr;  // L(m, C-2)
-  r.f[3] = K >= 4 && C >= 3 ? &A.w.tflag[tidx(A, m, C - 3)] : nullptr;  // L(m, C-3)
+  r.f[3] = nullptr;
   return r;
 }
 
@@ -679,35 +685,31 @@ __device__ __forceinline__ void publish_prev(const Args<F>& A, int64_t C, lds_i*
   }
 }
 
-// Waves 1-3 in phase A of step C (m = C+1), alongside the sweep:
-//   * publication of the previous step (publish_prev): at the start (FP64),
-//     or (FP32) at the end, after wave 1 has stored wave 0's block of
-//     L(C, C-1) from LDS (after its own loads, which would otherwise wait for
-//     that store);
-//   * tile (m, C-1): the helpers' sum over s <= C-4, here the terms s = C-3
-//     and C-2 (operands L(C-1, C-3) and L(C-1, C-2) still in LDS), then
-//     L(m, C-1) = tile L(C-1,C-1)^{-T} (the previous sweep's inverse, also
-//     still in LDS); row half h on wave 1+h;
-//   * tiles (m, C) and (m, m): the helpers' sums over s <= C-3; here s = C-2
-//     (wave 3, all blocks), then s = C-1 with the new L(m, C-1) (waves 1 and 2
-//     their row half, wave 3 block (1, 0) of (m, m)).
+// FP32 phase A of step C (m = C+1) on waves 1-3, alongside the sweep (the
+// FP32 accumulators are not operands, so tiles pass through LDS):
+//   * tile (m, C-1): the helpers' sum over s <= C-3 (P(m)), here the term
+//     s = C-2 (operand L(C-1, C-2) still in LDS), then L(m, C-1) = tile
+//     L(C-1,C-1)^{-T} (the previous sweep's inverse, also still in LDS); row
+//     half h on wave 1+h;
+//   * tiles (m, C) and (m, m): the helpers' sums over s <= C-3 (H(m)); here
+//     s = C-2 (wave 3, all blocks), then s = C-1 with the new L(m, C-1)
+//     (waves 1 and 2 their row half, wave 3 block (1, 0) of (m, m));
+//   * publication of the previous step (publish_prev) at the end, after wave
+//     1 has stored wave 0's block of L(C, C-1) from LDS (after its own loads,
+//     which would otherwise wait for that store).
 template <typename F>
-__device__ __forceinline__ void spine_prepare(const Args<F>& A, int64_t C, const SpineLds<F>& S, bool next,
-                                              lds_i* sync, lds_i* s_pub, lds_i* s_fail, int& early) {
+__device__ __forceinline__ void spine_prepare32(const Args<F>& A, int64_t C, const SpineLds<F>& S, bool next,
+                                                lds_i* sync, lds_i* s_pub, lds_i* s_fail, int& early) {
   const int wave = wave_id();
   const int lane = lane_id();
   const int K = A.K;
   const int64_t m = C + 1;
-  // FP32 schedule: wave 1 stores wave 0's block of L(C, C-1) (in the FP64 one
-  // waves 1 and 3 store all of L(C, C-1) after the previous sweep)
-  const bool copy0 = !acc_is_operand<F>() && C >= 1 && K >= 1;
-  if constexpr (acc_is_operand<F>()) publish_prev(A, C, s_pub);
+  const bool copy0 = C >= 1 && K >= 1;  // wave 1 stores wave 0's block of L(C, C-1)
   if (next) {
     const bool pre_o = K >= 4 && m >= 4;  // (m, C), (m, m) from H(m)
-    const bool pre_p = K >= 5 && C >= 4;  // (m, C-1) from P(m)
+    const bool pre_p = K >= 4 && m >= 4;  // (m, C-1) from P(m)
     const bool has_p = K >= 2 && C >= 1;  // tile (m, C-1) is inside the band
     const bool t2 = K >= 3 && C >= 2;     // term s = C-2: L(m, C-2)
-    const bool t3 = K >= 4 && C >= 3;     // term s = C-3 of (m, C-1): L(m, C-3)
     const int tag = (int)C + 1;
     // `early`: this lane's flag as read at the end of the previous step (1 if
     // none is needed); all set means no poll now
@@ -763,51 +765,32 @@ __device__ __forceinline__ void spine_prepare(const Args<F>& A, int64_t C, const
       }
     } else {
       const int h = wave - 1;
-      v4_t<F> out[2];  // row half h of L(m, C-1), blocks (h, 0) and (h, 1)
       if (has_p) {
         v4_t<F> pp[2];
-        F x3[T / 4], x4[T / 4], y1[2][T / 4], y2[2][T / 4];
+        F x3[T / 4], y1[2][T / 4];
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj)
           pp[bj] = blk_issue<F>(A, pre_p ? A.w.pre + C * 3 * T * T + 2 * T * T : nullptr, m, C - 1, h, bj);
         if (t2) term_load_x(A, m, C - 2, h, x3);
-        if (t3) term_load_x(A, m, C - 3, h, x4);
-        // L(C-1, C-2) and L(C-1, C-3), computed by the spine two steps ago,
-        // still sit in the buffers now called lcur and l2cur: read them before
-        // either wave overwrites those buffers
+        // L(C-1, C-2), computed by the spine two steps ago, still sits in the
+        // buffer now called lcur: both waves read it before either stages its
+        // tile there
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-          for (int q = 0; q < T / 4; ++q) {
-            const int ix = (4 * q + (lane >> 4)) * LP + 16 * bj + (lane & 15);
-            y1[bj][q] = t2 ? S.lcur[ix] : F(0);
-            y2[bj][q] = t3 ? S.l2cur[ix] : F(0);
-          }
+          for (int q = 0; q < T / 4; ++q)
+            y1[bj][q] = t2 ? S.lcur[(4 * q + (lane >> 4)) * LP + 16 * bj + (lane & 15)] : F(0);
         lds_signal(&sync[3 + h], tag);
         if (!lds_wait(&sync[4 - h], tag)) ok = false;
+        if (t2) {
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj) {
-          if (t3) pp[bj] = term_apply(x4, y2[bj], pp[bj]);
-          if (t2) pp[bj] = term_apply(x3, y1[bj], pp[bj]);
+          for (int bj = 0; bj < 2; ++bj) pp[bj] = term_apply(x3, y1[bj], pp[bj]);
         }
-        if constexpr (acc_is_operand<F>()) {
-          // L(m, C-1) = P L(C-1,C-1)^{-T} straight from the accumulators
-          // (L^{-T} upper triangular: block (h, 0) takes columns 0-15 of P only)
-          out[0] = out[1] = v4_t<F>{0, 0, 0, 0};
+        v4_t<F> out[2];  // row half h of L(m, C-1), blocks (h, 0) and (h, 1)
 #pragma unroll
-          for (int kb = 0; kb < 2; ++kb)
+        for (int bj = 0; bj < 2; ++bj) blk_to_lds(S.lcur, h, bj, pp[bj]);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int kk = 16 * kb + 4 * r + (lane >> 4);
-              if (kb == 0) out[0] = mfma_xyt(pp[0][r], S.linvt_prev[kk * LP + (lane & 15)], out[0]);
-              out[1] = mfma_xyt(pp[kb][r], S.linvt_prev[kk * LP + 16 + (lane & 15)], out[1]);
-            }
-        } else {
-#pragma unroll
-          for (int bj = 0; bj < 2; ++bj) blk_to_lds(S.lcur, h, bj, pp[bj]);
-#pragma unroll
-          for (int bj = 0; bj < 2; ++bj) out[bj] = blk_trsm_lds<F>(S.lcur, S.linvt_prev, h, bj, LP);
-        }
+        for (int bj = 0; bj < 2; ++bj) out[bj] = blk_trsm_lds<F>(S.lcur, S.linvt_prev, h, bj, LP);
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) {
           blk_to_lds(S.l2cur, h, bj, out[bj]);
@@ -819,42 +802,213 @@ __device__ __forceinline__ void spine_prepare(const Args<F>& A, int64_t C, const
       if (!lds_wait(&sync[2], tag)) {
         ok = false;
       } else if (has_p) {
-        if constexpr (acc_is_operand<F>()) {
-          // X = this wave's rows of L(m, C-1), still in registers
 #pragma unroll
-          for (int bj = 0; bj < 2; ++bj) {
-            v4_t<F> v = blk_from_lds<F>(S.acco, h, bj);
-#pragma unroll
-            for (int kb = 0; kb < 2; ++kb)
-#pragma unroll
-              for (int r = 0; r < 4; ++r)
-                v = mfma_xyt(-out[kb][r], S.lprev[(16 * kb + 4 * r + (lane >> 4)) * LP + 16 * bj + (lane & 15)], v);
-            blk_to_lds(S.acco, h, bj, v);
-          }
-          v4_t<F> v = blk_from_lds<F>(S.accd, h, h);
-#pragma unroll
-          for (int kb = 0; kb < 2; ++kb)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) v = mfma_xyt(-out[kb][r], out[kb][r], v);
-          blk_to_lds(S.accd, h, h, v);
-        } else {
-#pragma unroll
-          for (int bj = 0; bj < 2; ++bj) {
-            v4_t<F> v = blk_from_lds<F>(S.acco, h, bj);
-            v = blk_gemm_lds<F>(S.l2cur, S.lprev, h, bj, v);
-            blk_to_lds(S.acco, h, bj, v);
-          }
-          v4_t<F> v = blk_from_lds<F>(S.accd, h, h);
-          v = blk_gemm_lds<F>(S.l2cur, S.l2cur, h, h, v);
-          blk_to_lds(S.accd, h, h, v);
+        for (int bj = 0; bj < 2; ++bj) {
+          v4_t<F> v = blk_from_lds<F>(S.acco, h, bj);
+          v = blk_gemm_lds<F>(S.l2cur, S.lprev, h, bj, v);
+          blk_to_lds(S.acco, h, bj, v);
         }
+        v4_t<F> v = blk_from_lds<F>(S.accd, h, h);
+        v = blk_gemm_lds<F>(S.l2cur, S.l2cur, h, h, v);
+        blk_to_lds(S.accd, h, h, v);
       }
     }
     if (!ok && lane == 0) *s_fail = -2;
   } else if (wave == 1 && copy0) {
     ablk_store(A.a, C, C - 1, 0, 0, blk_from_lds<F>(S.lprev, 0, 0));
   }
-  if constexpr (!acc_is_operand<F>()) publish_prev(A, C, s_pub);
+  publish_prev(A, C, s_pub);
+  // the next step's flags, read now and used then (a load in flight meanwhile)
+  early = 1;
+  if (C + 2 < A.NB && lane < 4) {
+    const glb_i* f = step_flags(A, C + 1).f[lane];
+    if (f) early = __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Steady-state loads of the FP64 phase A: a dense workspace tile, or a band
+// tile that lies wholly inside the band, addressed as a uniform base (scalar
+// arithmetic) plus a lane offset, with no per-element test.
+template <typename F>
+__device__ __forceinline__ int wblk_lane_off() {
+  const int lane = lane_id();
+  return Prec<F>::acc_col0(lane) * T + (lane & 15);
+}
+template <typename F>
+__device__ __forceinline__ v4_t<F> wblk_ld(const glb_t<F>* tile, int lane_off, int bi, int bj) {
+  v4_t<F> v;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) v[r] = aload<F>(tile + ((16 * bj + Prec<F>::ACC_STEP * r) * T + 16 * bi) + lane_off);
+  return v;
+}
+// X operand (rows 16 bi .. of tile (Rx, s)) of a tile wholly inside the band
+// and above row n: the same elements as term_load_x.
+template <typename F>
+__device__ __forceinline__ void x_ld(const Args<F>& A, int64_t Rx, int64_t s, int bi, F (&xf)[T / 4]) {
+  const int lane = lane_id();
+  const int64_t l1 = A.a.ldab - 1;
+  const glb_t<F>* base = A.a.ab + (Rx * T + 16 * bi) + s * T * l1;
+  const int off = (lane & 15) + (lane >> 4) * (int)l1;
+#pragma unroll
+  for (int q = 0; q < T / 4; ++q) xf[q] = aload<F>(base + 4 * q * l1 + off);
+}
+// Whether tile (Rx, Rx-3) lies wholly inside the band and above row n.
+template <typename F>
+__device__ __forceinline__ bool x3_inside(const Args<F>& A, int64_t Rx) {
+  return A.a.k >= 4 * T - 1 && (Rx + 1) * T <= A.a.n;
+}
+
+// FP64 phase A of step C (m = C+1) on waves 1-3, alongside the sweep.  Wave
+// 1+h (h = 0, 1) owns row half h of the tiles (m, C-1) and (m, C), wave 3 the
+// tile (m, m), so that no wave waits for another's matrix-core work except
+// wave 3 for L(m, C-1):
+//   * row half h of (m, C-1): from P(m) (the helpers' sum over s <= C-3) or
+//     the band, the term s = C-2,
+//     then L(m, C-1) = that * L(C-1,C-1)^{-T} (the previous sweep's inverse,
+//     still in LDS): kept in registers, staged in l2cur and stored;
+//   * row half h of (m, C): from H(m) (the helpers' sum over s <= C-3) or the
+//     band, the terms s = C-2 and s = C-1 (the latter with L(m, C-1) straight
+//     from the registers), staged in acco;
+//   * wave 3, (m, m): from H(m) or the band, the term s = C-2, then, once
+//     both row halves of L(m, C-1) are in l2cur, s = C-1; staged in accd.
+template <typename F>
+__device__ __forceinline__ void spine_prepare64(const Args<F>& A, int64_t C, const SpineLds<F>& S, bool next,
+                                                lds_i* sync, lds_i* s_pub, lds_i* s_fail, int& early) {
+  const int wave = wave_id();
+  const int lane = lane_id();
+  const int K = A.K;
+  const int64_t m = C + 1;
+  publish_prev(A, C, s_pub);
+  if (next) {
+    const bool pre_o = K >= 4 && m >= 4;  // (m, C), (m, m) from H(m)
+    const bool pre_p = K >= 4 && m >= 4;  // (m, C-1) from P(m)
+    const bool has_p = K >= 2 && C >= 1;  // tile (m, C-1) is inside the band
+    const bool t2 = K >= 3 && C >= 2;     // term s = C-2: L(m, C-2)
+    // (the term s = C-3 of (m, C-1) is in P(m) wherever the band holds it)
+    const int tag = (int)C + 1;
+    // `early`: this lane's flag as read at the end of the previous step (1 if
+    // none is needed); all set means no poll now
+    bool ok = true;
+    if (__ballot(early == 0) != 0) {
+      const StepFlags<F> fl = step_flags(A, C);
+      ok = wave_wait4(fl.f[0], fl.f[1], fl.f[2], fl.f[3], A.w);
+    } else {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");  // keeps the operand loads below the flags
+    }
+    const int loff = wblk_lane_off<F>();
+    const bool x3_in = t2 && x3_inside(A, m);
+    if (wave == 3) {
+      v4_t<F> ad[3];  // blocks (0,0), (1,0), (1,1) of (m, m)
+      F x3[2][T / 4];
+      if (pre_o) {
+#pragma unroll
+        for (int b = 0; b < 3; ++b) ad[b] = wblk_ld<F>(A.w.pre + m * 3 * T * T + T * T, loff, b >= 1, b == 2);
+      } else {
+#pragma unroll
+        for (int b = 0; b < 3; ++b) ad[b] = blk_issue<F>(A, nullptr, m, m, b >= 1, b == 2);
+      }
+      if (x3_in) {
+        x_ld(A, m, C - 2, 0, x3[0]);
+        x_ld(A, m, C - 2, 1, x3[1]);
+      } else if (t2) {
+        term_load_x(A, m, C - 2, 0, x3[0]);
+        term_load_x(A, m, C - 2, 1, x3[1]);
+      }
+      if (!pre_o) {
+#pragma unroll
+        for (int b = 0; b < 3; ++b) blk_ident(A.a, m, m, b >= 1, b == 2, ad[b]);
+      }
+      if (t2) {
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+          for (int q = 0; q < T / 4; ++q) ad[b] = mfma_xyt(-x3[b >= 1][q], x3[b == 2][q], ad[b]);
+      }
+      if (has_p) {
+        if (!lds_wait(&sync[0], tag) || !lds_wait(&sync[1], tag)) {
+          ok = false;
+        } else {
+#pragma unroll
+          for (int b = 0; b < 3; ++b) ad[b] = blk_gemm_lds<F>(S.l2cur, S.l2cur, b >= 1, b == 2, ad[b]);
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < 3; ++b) blk_to_lds(S.accd, b >= 1, b == 2, ad[b]);
+    } else {
+      const int h = wave - 1;
+      v4_t<F> ao[2];   // row half h of (m, C)
+      v4_t<F> out[2];  // row half h of L(m, C-1)
+      F x3[T / 4];
+      if (pre_o) {
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) ao[bj] = wblk_ld<F>(A.w.pre + m * 3 * T * T, loff, h, bj);
+      } else {
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) ao[bj] = blk_issue<F>(A, nullptr, m, C, h, bj);
+      }
+      if (x3_in) x_ld(A, m, C - 2, h, x3);
+      else if (t2) term_load_x(A, m, C - 2, h, x3);
+      if (has_p) {
+        v4_t<F> pp[2];
+        F y1[2][T / 4];
+        if (pre_p) {
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj) pp[bj] = wblk_ld<F>(A.w.pre + C * 3 * T * T + 2 * T * T, loff, h, bj);
+        } else {
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj) pp[bj] = blk_issue<F>(A, nullptr, m, C - 1, h, bj);
+        }
+        // L(C-1, C-2), computed by the spine two steps ago, still sits in lcur
+        // (overwritten only in phase BC)
+        if (t2) {
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int q = 0; q < T / 4; ++q) y1[bj][q] = S.lcur[(4 * q + (lane >> 4)) * LP + 16 * bj + (lane & 15)];
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj) pp[bj] = term_apply(x3, y1[bj], pp[bj]);
+        }
+        // L(m, C-1) = P L(C-1,C-1)^{-T} straight from the accumulators
+        // (L^{-T} upper triangular: block (h, 0) takes columns 0-15 of P only)
+        out[0] = out[1] = v4_t<F>{0, 0, 0, 0};
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int kk = 16 * kb + 4 * r + (lane >> 4);
+            if (kb == 0) out[0] = mfma_xyt(pp[0][r], S.linvt_prev[kk * LP + (lane & 15)], out[0]);
+            out[1] = mfma_xyt(pp[kb][r], S.linvt_prev[kk * LP + 16 + (lane & 15)], out[1]);
+          }
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+          blk_to_lds(S.l2cur, h, bj, out[bj]);
+          ablk_store(A.a, m, C - 1, h, bj, out[bj]);
+        }
+        lds_signal(&sync[h], tag);
+      }
+      // (m, C): s = C-2 with L(C, C-2) (l2prev), s = C-1 with L(C, C-1) (lprev)
+      if (t2) {
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+          for (int q = 0; q < T / 4; ++q)
+            ao[bj] = mfma_xyt(-x3[q], S.l2prev[(4 * q + (lane >> 4)) * LP + 16 * bj + (lane & 15)], ao[bj]);
+      }
+      if (has_p) {
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+          for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              ao[bj] = mfma_xyt(-out[kb][r], S.lprev[(16 * kb + 4 * r + (lane >> 4)) * LP + 16 * bj + (lane & 15)],
+                                ao[bj]);
+      }
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) blk_to_lds(S.acco, h, bj, ao[bj]);
+    }
+    if (!ok && lane == 0) *s_fail = -2;
+  }
   // the next step's flags, read now and used then (a load in flight meanwhile)
   early = 1;
   if (C + 2 < A.NB && lane < 4) {
@@ -951,7 +1105,8 @@ __device__ __attribute__((noinline)) void spine_waves123(const Args<F>& A_, cons
     const bool next = C + 1 < A.NB;
     const unsigned long long t0 = stamp(prof);
     // phase A
-    spine_prepare(A, C, S, next, sync, s_pub, s_fail, early);
+    if constexpr (acc_is_operand<F>()) spine_prepare64(A, C, S, next, sync, s_pub, s_fail, early);
+    else spine_prepare32(A, C, S, next, sync, s_pub, s_fail, early);
     const unsigned long long t1 = stamp(prof);
     lds_barrier();
     if (prof) {
@@ -1065,12 +1220,11 @@ __device__ void spine(const Args<F>& A, lds_t<F>* base, lds_i* s_fail, lds_i* s_
 // ---------------------------------------------------------------- kernel
 
 // Ticket order: 0 = spine; then per column C the tiles O(C+3..C+K, C) in
-// pairs (the last one alone when their count is odd), with H(C+4) after the
-// first pair and P(C+5) after the second (their last terms use those pairs'
-// tiles).
+// pairs (the last one alone when their count is odd), with H(C+4) and P(C+4)
+// after the first pair (their last terms use that pair's tiles).
 __host__ __device__ __forceinline__ unsigned off_pairs(int K) { return K >= 3 ? (unsigned)(K - 1) / 2u : 0u; }
 __host__ __device__ __forceinline__ unsigned tickets_per_column(int K) {
-  return off_pairs(K) + (K >= 4 ? 1u : 0u) + (K >= 5 ? 1u : 0u);
+  return off_pairs(K) + (K >= 4 ? 2u : 0u);
 }
 
 // kind 1: tile (R, C); kind 3: tiles (R, C) and (R+1, C); kind 2: H(R); kind 4: P(R).
@@ -1089,16 +1243,8 @@ __device__ __forceinline__ void decode(const Args<F>& A, unsigned t, int& kind, 
   }
   if (A.K >= 4) {
     if (k == 0) { kind = 2; R = C + 4; return; }
-    --k;
-  }
-  if (np >= 2) {
-    if (k == 0) goto off;
-    --k;
-    pair = 2;
-  }
-  if (A.K >= 5) {
-    if (k == 0) { kind = 4; R = C + 5; return; }
-    --k;
+    if (k == 1) { kind = 4; R = C + 4; return; }
+    k -= 2;
   }
   pair += k;
 off:
