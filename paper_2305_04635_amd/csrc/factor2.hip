@@ -582,7 +582,8 @@ __device__ __forceinline__ void spine_sweep(lds_t<F>* diag, lds_t<F>* sd, lds_t<
 
 // L(C,C) from LDS (column-major, pitch LP) to the band, lower triangle: lane
 // (r, h) stores column 2p + h of row r.  Not waited for; four values at a
-// time keep the registers it needs inside the kernel few.
+// time keep the registers it needs inside the kernel few (all sixteen at
+// once made wave 0 spill).
 template <typename F>
 __device__ __forceinline__ void store_lcc(const lds_t<F>* lcc, int64_t C, const BandT<F>& a) {
   const int lane = lane_id();
@@ -980,19 +981,27 @@ __device__ __forceinline__ void spine_prepare64(const Args<F>& A, int64_t C, con
             out[1] = mfma_xyt(pp[kb][r], S.linvt_prev[kk * LP + 16 + (lane & 15)], out[1]);
           }
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj) {
-          blk_to_lds(S.l2cur, h, bj, out[bj]);
-          ablk_store(A.a, m, C - 1, h, bj, out[bj]);
-        }
+        for (int bj = 0; bj < 2; ++bj) blk_to_lds(S.l2cur, h, bj, out[bj]);
         lds_signal(&sync[h], tag);
       }
-      // (m, C): s = C-2 with L(C, C-2) (l2prev), s = C-1 with L(C, C-1) (lprev)
+      // (m, C): s = C-2 with L(C, C-2) (l2prev), s = C-1 with L(C, C-1)
+      // (lprev); the stores of L(m, C-1) go out between the matrix-core
+      // steps of the first term, which leave the wave idle while each runs
+      const RunT<F> run0 = acc_run(A.a, m, C - 1, h, 0), run1 = acc_run(A.a, m, C - 1, h, 1);
       if (t2) {
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-          for (int q = 0; q < T / 4; ++q)
+          for (int q = 0; q < T / 4; ++q) {
             ao[bj] = mfma_xyt(-x3[q], S.l2prev[(4 * q + (lane >> 4)) * LP + 16 * bj + (lane & 15)], ao[bj]);
+            if (has_p && (q & 1)) {
+              const RunT<F>& run = bj ? run1 : run0;
+              if (run.in(q >> 1)) astore(run.at(q >> 1), out[bj][q >> 1]);
+            }
+          }
+      } else if (has_p) {
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) ablk_store(A.a, m, C - 1, h, bj, out[bj]);
       }
       if (has_p) {
 #pragma unroll
@@ -1120,33 +1129,47 @@ __device__ __attribute__((noinline)) void spine_waves123(const Args<F>& A_, cons
     }
     if constexpr (acc_is_operand<F>()) {
       // phase BC: wave w takes block (ci, cj) of the next diagonal tile,
-      // (0,0), (1,0), (1,1) for waves 1, 2, 3, and computes the row blocks of
-      // L(C+1, C) = acco * L(C,C)^{-T} that its last term needs (wave 2 both,
-      // the others their own); their accumulators are the operands of that
-      // term, so no barrier separates the trsm from it.  Waves 1 and 3 store
-      // their row block and stage it for the next step.  The new tile goes
-      // to accd's buffer, each wave over the block it read.
+      // (0,0), (1,0), (1,1) for waves 1, 2, 3, and computes row block ci of
+      // L(C+1, C) = acco * L(C,C)^{-T}; its accumulators are the operands of
+      // that block's last term, so no barrier separates the trsm from it.
+      // Waves 1 and 3 stage their row block (for wave 2, which takes row
+      // block 0 from there once wave 1 signals, and for the next step) and
+      // store it.  The new tile goes to accd's buffer, each wave over the
+      // block it read.
       const int ci = wave >= 2, cj = wave == 3;
       v4_t<F> acc = blk_from_lds<F>(S.accd, ci, cj);
       if (A.K >= 1) {
-        v4_t<F> oi[2], oj[2];
+        v4_t<F> oi[2];
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb) oi[kb] = blk_trsm_lds(S.acco, S.linvt, ci, kb, LP);
         if (wave == 2) {
+          // row block 1 in registers, row block 0 from wave 1 through LDS
+          if (!lds_wait(&sync[3], (int)C + 1)) {
+            if (lane_id() == 0) *s_fail = -2;
+          } else {
 #pragma unroll
-          for (int kb = 0; kb < 2; ++kb) oj[kb] = blk_trsm_lds(S.acco, S.linvt, 0, kb, LP);
+            for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+              for (int r = 0; r < 4; ++r)
+                acc = mfma_xyt(-oi[kb][r], S.lcur[(16 * kb + 4 * r + (lane_id() >> 4)) * LP + (lane_id() & 15)], acc);
+          }
         } else {
 #pragma unroll
-          for (int kb = 0; kb < 2; ++kb) {
-            oj[kb] = oi[kb];
-            blk_to_lds(S.lcur, ci, kb, oi[kb]);
-            ablk_store(a, C + 1, C, ci, kb, oi[kb]);
-          }
+          for (int kb = 0; kb < 2; ++kb) blk_to_lds(S.lcur, ci, kb, oi[kb]);
+          if (wave == 1) lds_signal(&sync[3], (int)C + 1);
+          // the stores of the row block go out one per matrix-core step of
+          // the last term, whose dependent steps would otherwise leave the
+          // wave idle while each one runs
+          const RunT<F> run0 = acc_run(a, C + 1, C, ci, 0), run1 = acc_run(a, C + 1, C, ci, 1);
+#pragma unroll
+          for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              acc = mfma_xyt(-oi[kb][r], oi[kb][r], acc);
+              const RunT<F>& run = kb ? run1 : run0;
+              if (run.in(r)) astore(run.at(r), oi[kb][r]);
+            }
         }
-#pragma unroll
-        for (int kb = 0; kb < 2; ++kb)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) acc = mfma_xyt(-oi[kb][r], oj[kb][r], acc);
       }
       blk_to_lds<F>(S.accd, ci, cj, acc);
       lds_t<F>* t = S.diag; S.diag = S.accd; S.accd = t;
