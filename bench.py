@@ -771,6 +771,8 @@ def bench_mixed(args):
         m_ms, f_ms = float(np.median(ms_m)), float(np.median(ms_64))
         total_mixed += m_ms
         total_fp64 += f_ms
+        if d == 1:
+            parts = mixed_parts(bc, dab, db, n, k, nrhs, dev)
         per_d.append({"d": d, "mixed_ms": round(m_ms, 3), "fp64_factor_solve_ms": round(f_ms, 3),
                       "iterations": it, "fallback": fb,
                       "mixed_backward_error": bwd_err(xh), "fp64_backward_error": bwd_err(x64h),
@@ -786,9 +788,43 @@ def bench_mixed(args):
         "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": "mixed-precision solve, n=%d, k=%d, nrhs=%d, A = L0 L0^T + 10^(-2d)||A|| I, "
                                "L0 diagonal 10^U[-d,0], d = 1..5" % (n, k, nrhs),
-                   "fp64_factor_solve_ms_sum": round(total_fp64, 3), "per_d": per_d},
+                   "fp64_factor_solve_ms_sum": round(total_fp64, 3), "per_d": per_d,
+                   "parts_ms_d1": parts},
     }
     print(json.dumps(line))
+
+
+def mixed_parts(bc, dab, db, n, k, nrhs, dev):
+    """The pieces of the mixed and FP64 paths timed alone (median of 3, HIP events) on one
+    matrix: the FP32 factor, the FP64 factor and one solve with all right-hand sides on the
+    FP64 factor (the mixed path runs that solve once plus once per correction)."""
+    import numpy as np
+    import torch
+
+    info = torch.zeros(1, dtype=torch.int64, device=dev)
+    a32 = dab.float()
+    l32 = torch.empty_like(a32)
+    l64 = torch.empty_like(dab)
+    x = torch.empty_like(db)
+
+    def timed(prep, run):
+        ts = []
+        for _ in range(4):
+            prep()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            run()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return round(float(np.median(ts[1:])), 3)
+
+    f32 = timed(lambda: l32.copy_(a32), lambda: bc.factor_f32(l32, n, k, info))
+    f64 = timed(lambda: l64.copy_(dab), lambda: bc.factor_async(l64, n, k, info))
+    solve = timed(lambda: x.copy_(db), lambda: bc.solve_async(l64, n, k, x, nrhs=nrhs))
+    solve1 = timed(lambda: x.copy_(db), lambda: bc.solve_async(l64, n, k, x, nrhs=1))
+    return {"fp32_factor": f32, "fp64_factor": f64, "solve_all_rhs": solve, "solve_one_rhs": solve1}
 
 
 def bench_spine_profile(args):
