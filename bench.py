@@ -841,7 +841,7 @@ def bench_spine_profile(args):
     per_k = []
     for k in ks:
         d = bc.spine_profile(args.n, k, reps=3)
-        w0 = d["sweep"] + d["w0_wait"] + d["phase_b"] + d["phase_c"]
+        w0 = d["sweep"] + d["w0_wait"] + d["bc_w0"] + d["bc_wait"]
         d["k"] = k
         d["w0_step_cycles"] = w0
         d["clock_ghz"] = w0 * d["steps"] / (d["factor_ms"] * 1e-3) / 1e9

@@ -163,8 +163,10 @@ int64_t bandchol_pivot_chain_ns(int64_t steps, double* ns_per_step);
  * rule where that is the walk) and the spine's phase times recorded (shader
  * clock, s_memtime), and writes out[0..12]: per step of 32 columns, the cycles
  * of wave 0's diagonal-tile sweep (0), its wait for waves 1-3 at the end of
- * phase A (1), phase B (2), phase C (3); for waves 1, 2, 3 the cycles of
- * their phase-A work and of their wait at its end (4..9); the number of steps
+ * phase A (1), its work in phase BC (the stores of L(C,C) and its inverse,
+ * while waves 1-3 finish the next diagonal tile) (2) and its wait for them
+ * at the end of that phase (3); for waves 1, 2, 3 the cycles of their
+ * phase-A work and of their wait at its end (4..9); the number of steps
  * (10); the last factor's time in ms (11); its workgroup count (12).  n >= 2
  * (-1), k >= 1 (-2), 1 <= reps <= 100 (-3), out with cap >= 13 (-4).
  * Allocates the test band; synchronous; not under stream capture.

@@ -201,7 +201,7 @@ def batch_tune(ns, ks, reps=3, max_buckets=4):
     return float(ms.value)
 
 
-SPINE_PROFILE_KEYS = ("sweep", "w0_wait", "phase_b", "phase_c", "w1_work", "w1_wait", "w2_work", "w2_wait",
+SPINE_PROFILE_KEYS = ("sweep", "w0_wait", "bc_w0", "bc_wait", "w1_work", "w1_wait", "w2_work", "w2_wait",
                       "w3_work", "w3_wait")
 
 

@@ -59,10 +59,11 @@ struct Ws {
   unsigned long long* prof;  // if not null: the spine's phase times, summed over the steps (s_memtime)
 };
 
-// Slots of Ws::prof: wave 0's sweep, its wait at the end of phase A, phases B
-// and C; per wave w = 1..3 its phase-A work and its wait at the end of phase A;
-// the number of steps summed.
-enum { PROF_SWEEP, PROF_W0_WAIT, PROF_B, PROF_C, PROF_W1_WORK, PROF_W1_WAIT, PROF_W2_WORK, PROF_W2_WAIT,
+// Slots of Ws::prof: wave 0's sweep, its wait at the end of phase A, its work
+// in phase BC and its wait at the end of it (FP32 schedule: phases B and C);
+// per wave w = 1..3 its phase-A work and its wait at the end of phase A; the
+// number of steps summed.
+enum { PROF_SWEEP, PROF_W0_WAIT, PROF_BC_W0, PROF_BC_WAIT, PROF_W1_WORK, PROF_W1_WAIT, PROF_W2_WORK, PROF_W2_WAIT,
        PROF_W3_WORK, PROF_W3_WAIT, PROF_STEPS, PROF_SLOTS };
 
 __device__ __forceinline__ unsigned long long stamp(bool on) { return on ? __builtin_amdgcn_s_memtime() : 0ull; }
@@ -1053,8 +1054,8 @@ __device__ __attribute__((noinline)) void spine_wave0(const Args<F>& A_, const S
     const unsigned long long t2 = stamp(prof);
     if (*s_fail != -1 || !next) {
       if (prof && lane_id() == 0) {
-        A.w.prof[PROF_SWEEP] = p_sweep, A.w.prof[PROF_W0_WAIT] = p_wait, A.w.prof[PROF_B] = p_b;
-        A.w.prof[PROF_C] = p_c, A.w.prof[PROF_STEPS] = steps;
+        A.w.prof[PROF_SWEEP] = p_sweep, A.w.prof[PROF_W0_WAIT] = p_wait, A.w.prof[PROF_BC_W0] = p_b;
+        A.w.prof[PROF_BC_WAIT] = p_c, A.w.prof[PROF_STEPS] = steps;
       }
       return;
     }

@@ -124,7 +124,7 @@ def test_spine_profile_accounts_for_the_step(k):
     d = bc.spine_profile(n, k, reps=2)
     nb = (n + 31) // 32
     assert d["steps"] == nb - 1
-    w0 = d["sweep"] + d["w0_wait"] + d["phase_b"] + d["phase_c"]
+    w0 = d["sweep"] + d["w0_wait"] + d["bc_w0"] + d["bc_wait"]
     ghz = w0 * d["steps"] / (d["factor_ms"] * 1e-3) / 1e9
     assert 0.5 < ghz < 3.5, ghz
     for w in (1, 2, 3):
