@@ -549,9 +549,13 @@ __device__ __forceinline__ void spine_sweep(lds_t<F>* diag, lds_t<F>* sd, lds_t<
                                             unsigned long long* first_fail, glb_i* abort_flag, lds_i* s_fail) {
   const int lane = lane_id();
   if (flag_prev) store_linvt(linvt_prev, lt_prev);
+  // every lane reads (lanes >= T a row they then drop for the identity), so
+  // that no read sits behind a branch
   F row[T];
 #pragma unroll
-  for (int c = 0; c < T; ++c) row[c] = lane < T ? diag[c * LP + lane] : ((lane - T) == c ? F(1) : F(0));
+  for (int c = 0; c < T; ++c) row[c] = diag[c * LP + (lane & (T - 1))];
+#pragma unroll
+  for (int c = 0; c < T; ++c) row[c] = lane < T ? row[c] : ((lane - T) == c ? F(1) : F(0));
   if (flag_stored) {
     wait_vmem();
     if (lane == 0) raise_flag(flag_stored);
