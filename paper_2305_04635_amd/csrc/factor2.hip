@@ -97,6 +97,18 @@ __device__ __forceinline__ __attribute__((address_space(3))) P* uni_lds(__attrib
   return (__attribute__((address_space(3))) P*)(uintptr_t)(unsigned)uni((int)(unsigned)(uintptr_t)p);
 }
 
+// The fields that the spine's waves 1-3 use in every step, in scalar
+// registers; the rest stay in vector registers (all of them in scalar
+// registers spilled scalar registers into vector lanes in those waves).
+template <typename F>
+__device__ __forceinline__ Args<F> uniform_step(const Args<F>& A_) {
+  Args<F> A = A_;
+  A.a.ab = uni(A_.a.ab), A.a.n = uni(A_.a.n), A.a.k = uni(A_.a.k), A.a.ldab = uni(A_.a.ldab);
+  A.NB = uni(A_.NB), A.K = uni(A_.K);
+  A.w.tflag = uni(A_.w.tflag), A.w.hflag = uni(A_.w.hflag), A.w.pflag = uni(A_.w.pflag), A.w.pre = uni(A_.w.pre);
+  return A;
+}
+
 template <typename F>
 __device__ __forceinline__ Args<F> uniform(const Args<F>& A_) {
   Args<F> A;
@@ -1108,8 +1120,8 @@ __device__ __attribute__((noinline)) void spine_wave0(const Args<F>& A_, const S
 template <typename F>
 __device__ __attribute__((noinline)) void spine_waves123(const Args<F>& A_, const SpineLds<F>& S_, lds_i* sync,
                                                          lds_i* s_pub, lds_i* s_fail) {
-  const Args<F> A = uniform(A_);
-  SpineLds<F> S = uniform(S_);
+  const Args<F> A = uniform_step(A_);
+  SpineLds<F> S = S_;
   const BandT<F>& a = A.a;
   const int wave = wave_id();
   int early = 0;
