@@ -282,17 +282,23 @@ __device__ __forceinline__ bool apply_terms(const Args<F>& A, int64_t R, int64_t
   return true;
 }
 
-// Trsm of the accumulator tile held across the 4 waves: out = acc * L(C,C)^{-T}
-// (L^{-T} column-major in global memory).
+// The operand fragments of block column bj of L(C,C)^{-T} (column-major in
+// global memory; upper triangular, so only the first 4 bj + 4 k-steps), read
+// as soon as its flag is seen so that they arrive while the task stages its
+// accumulators; used by trsm_frags for every tile of the task.
 template <typename F>
-__device__ __forceinline__ v4_t<F> trsm_from_lds(const lds_t<F>* x, const glb_t<F>* linvt_g, int bi, int bj) {
+__device__ __forceinline__ void linvt_frags(const glb_t<F>* linvt_g, int bj, F (&yf)[T / 4]) {
   const int lane = lane_id();
-  v4_t<F> out = {0, 0, 0, 0};
   const int qmax = 4 * bj + 4;
-  F yf[T / 4];
 #pragma unroll
   for (int q = 0; q < T / 4; ++q)
     yf[q] = (q < qmax) ? aload<F>(linvt_g + (16 * bj + (lane & 15)) * T + 4 * q + (lane >> 4)) : F(0);
+}
+template <typename F>
+__device__ __forceinline__ v4_t<F> trsm_frags(const lds_t<F>* x, const F (&yf)[T / 4], int bi, int bj) {
+  const int lane = lane_id();
+  v4_t<F> out = {0, 0, 0, 0};
+  const int qmax = 4 * bj + 4;
 #pragma unroll
   for (int q = 0; q < T / 4; ++q)
     if (q < qmax) out = mfma_xyt(x[(4 * q + (lane >> 4)) * LP + 16 * bi + (lane & 15)], yf[q], out);
@@ -312,11 +318,13 @@ __device__ __attribute__((noinline)) void task_off(const Args<F>& A_, int64_t R,
   const int64_t s0 = R - A.K > 0 ? R - A.K : 0;
   int ok = apply_terms(A, R, C, s0, C, bi, bj, acc) ? 1 : 0;
   if (ok) ok = wave_wait(&A.w.tflag[tidx(A, C, C)], A.w) ? 1 : 0;
+  F yf[T / 4];
+  linvt_frags<F>(A.w.linvt + C * T * T, bj, yf);
   blk_to_lds(stage, bi, bj, acc);
   if (!ok && lane_id() == 0) *s_ok = 0;
   __syncthreads();
   if (*s_ok == 0) return;
-  const v4_t<F> out = trsm_from_lds<F>(stage, A.w.linvt + C * T * T, bi, bj);
+  const v4_t<F> out = trsm_frags<F>(stage, yf, bi, bj);
   ablk_store(A.a, R, C, bi, bj, out);
   wait_vmem();
   __syncthreads();
@@ -387,13 +395,15 @@ __device__ __attribute__((noinline)) void task_off2(const Args<F>& A_, int64_t R
   const int64_t s0 = R - A.K > 0 ? R - A.K : 0;
   int ok = apply_terms2(A, R, C, s0, C, bi, bj, acc0, acc1) ? 1 : 0;
   if (ok) ok = wave_wait(&A.w.tflag[tidx(A, C, C)], A.w) ? 1 : 0;
+  F yf[T / 4];  // one read of the inverse for both tiles
+  linvt_frags<F>(A.w.linvt + C * T * T, bj, yf);
   blk_to_lds(stage, bi, bj, acc0);
   blk_to_lds(stage + T * LP, bi, bj, acc1);
   if (!ok && lane_id() == 0) *s_ok = 0;
   __syncthreads();
   if (*s_ok == 0) return;
-  const v4_t<F> out0 = trsm_from_lds<F>(stage, A.w.linvt + C * T * T, bi, bj);
-  const v4_t<F> out1 = trsm_from_lds<F>(stage + T * LP, A.w.linvt + C * T * T, bi, bj);
+  const v4_t<F> out0 = trsm_frags<F>(stage, yf, bi, bj);
+  const v4_t<F> out1 = trsm_frags<F>(stage + T * LP, yf, bi, bj);
   ablk_store(A.a, R, C, bi, bj, out0);
   ablk_store(A.a, R + 1, C, bi, bj, out1);
   wait_vmem();
