@@ -140,14 +140,43 @@ __device__ __forceinline__ bool wave_wait(const glb_i* f, const Ws<F>& w) {
   glb_i* const abort_flag = w.abort_flag;
   long long spins = 0;
   while (!aflag(f)) {
-    if (aflag(abort_flag)) return false;
-    if (++spins > SPIN_LIMIT) {
-      __hip_atomic_store(abort_flag, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      return false;
+    // the abort flag and the bound every 16th poll: a poll is one memory
+    // round trip, and a second load per poll would double the latency at
+    // which a raised flag is seen
+    if ((++spins & 15) == 0) {
+      if (aflag(abort_flag)) return false;
+      if (spins > SPIN_LIMIT) {
+        __hip_atomic_store(abort_flag, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return false;
+      }
     }
     __builtin_amdgcn_s_sleep(1);
   }
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");  // keeps later loads below the wait
+  return true;
+}
+
+// Up to four flags (null: none) polled in one round trip; bounded like wave_wait.
+template <typename F>
+__device__ __forceinline__ bool wave_wait4(const glb_i* f0, const glb_i* f1, const glb_i* f2, const glb_i* f3,
+                                           const Ws<F>& w) {
+  const int lane = lane_id();
+  const glb_i* mine = lane == 0 ? f0 : lane == 1 ? f1 : lane == 2 ? f2 : lane == 3 ? f3 : nullptr;
+  long long spins = 0;
+  for (;;) {
+    int v = 1;
+    if (mine) v = __hip_atomic_load(mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (__ballot(v == 0) == 0) break;
+    if ((++spins & 15) == 0) {  // as in wave_wait
+      if (aflag(w.abort_flag)) return false;
+      if (spins > SPIN_LIMIT) {
+        __hip_atomic_store(w.abort_flag, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return false;
+      }
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   return true;
 }
 
@@ -261,8 +290,9 @@ __device__ __forceinline__ bool apply_terms(const Args<F>& A, int64_t R, int64_t
     const unsigned long long bad = __ballot(lane < span && f == 0);
     int64_t e = s + (bad ? (int)__builtin_ctzll(bad) : span);
     if (e == s) {
-      if (!wave_wait(&A.w.tflag[tidx(A, R, s)], A.w)) return false;
-      if (C != R && !wave_wait(&A.w.tflag[tidx(A, C, s)], A.w)) return false;
+      if (!wave_wait4<F>(&A.w.tflag[tidx(A, R, s)], C != R ? &A.w.tflag[tidx(A, C, s)] : nullptr, nullptr, nullptr,
+                         A.w))
+        return false;
       e = s + 1;
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");  // keeps the operand loads below the flags
@@ -294,14 +324,22 @@ __device__ __forceinline__ void linvt_frags(const glb_t<F>* linvt_g, int bj, F (
   for (int q = 0; q < T / 4; ++q)
     yf[q] = (q < qmax) ? aload<F>(linvt_g + (16 * bj + (lane & 15)) * T + 4 * q + (lane >> 4)) : F(0);
 }
+// out = (block row bi of the staged tile x) * (block column bj of the
+// inverse); the tile's fragments are all read before the first matrix-core
+// step (the scheduling barrier keeps the compiler from sinking each read
+// next to its step, with a full LDS wait before each).
 template <typename F>
 __device__ __forceinline__ v4_t<F> trsm_frags(const lds_t<F>* x, const F (&yf)[T / 4], int bi, int bj) {
   const int lane = lane_id();
+  F xf[T / 4];
+#pragma unroll
+  for (int q = 0; q < T / 4; ++q) xf[q] = x[(4 * q + (lane >> 4)) * LP + 16 * bi + (lane & 15)];
+  __builtin_amdgcn_sched_barrier(0);
   v4_t<F> out = {0, 0, 0, 0};
   const int qmax = 4 * bj + 4;
 #pragma unroll
   for (int q = 0; q < T / 4; ++q)
-    if (q < qmax) out = mfma_xyt(x[(4 * q + (lane >> 4)) * LP + 16 * bi + (lane & 15)], yf[q], out);
+    if (q < qmax) out = mfma_xyt(xf[q], yf[q], out);
   return out;
 }
 
@@ -354,8 +392,9 @@ __device__ __forceinline__ bool apply_terms2(const Args<F>& A, int64_t R, int64_
     const unsigned long long bad = __ballot(lane < span && f == 0);
     int64_t e = s + (bad ? (int)__builtin_ctzll(bad) : span);
     if (e == s) {
-      if (!wave_wait(&A.w.tflag[tidx(A, R, s)], A.w) || !wave_wait(&A.w.tflag[tidx(A, C, s)], A.w)) return false;
-      if (s >= s_in1 && !wave_wait(&A.w.tflag[tidx(A, R + 1, s)], A.w)) return false;
+      if (!wave_wait4<F>(&A.w.tflag[tidx(A, R, s)], &A.w.tflag[tidx(A, C, s)],
+                         s >= s_in1 ? &A.w.tflag[tidx(A, R + 1, s)] : nullptr, nullptr, A.w))
+        return false;
       e = s + 1;
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");  // keeps the operand loads below the flags
@@ -468,7 +507,7 @@ __device__ __attribute__((noinline)) void task_pre(const Args<F>& A_, int64_t m,
     const unsigned long long bad = __ballot(lane < span && f == 0);
     int64_t e = s + (bad ? (int)__builtin_ctzll(bad) : span);
     if (e == s) {
-      if (!wave_wait(&A.w.tflag[tidx(A, m, s)], A.w) || !wave_wait(&A.w.tflag[tidx(A, m - 1, s)], A.w)) {
+      if (!wave_wait4<F>(&A.w.tflag[tidx(A, m, s)], &A.w.tflag[tidx(A, m - 1, s)], nullptr, nullptr, A.w)) {
         ok = 0;
         break;
       }
@@ -636,28 +675,6 @@ __device__ __forceinline__ void lds_barrier() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
   __builtin_amdgcn_s_barrier();
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
-
-// Up to four flags (null: none) polled in one round trip; bounded like wave_wait.
-template <typename F>
-__device__ __forceinline__ bool wave_wait4(const glb_i* f0, const glb_i* f1, const glb_i* f2, const glb_i* f3,
-                                           const Ws<F>& w) {
-  const int lane = lane_id();
-  const glb_i* mine = lane == 0 ? f0 : lane == 1 ? f1 : lane == 2 ? f2 : lane == 3 ? f3 : nullptr;
-  long long spins = 0;
-  for (;;) {
-    int v = 1;
-    if (mine) v = __hip_atomic_load(mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (__ballot(v == 0) == 0) break;
-    if (aflag(w.abort_flag)) return false;
-    if (++spins > SPIN_LIMIT) {
-      __hip_atomic_store(w.abort_flag, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      return false;
-    }
-    __builtin_amdgcn_s_sleep(1);
-  }
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-  return true;
 }
 
 // The helper flags step C of the spine waits for (null: not needed there).
