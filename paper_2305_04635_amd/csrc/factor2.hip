@@ -1286,12 +1286,15 @@ __device__ void spine(const Args<F>& A, lds_t<F>* base, lds_i* s_fail, lds_i* s_
 
 // ---------------------------------------------------------------- kernel
 
-// Ticket order: 0 = spine; then per column C the tiles O(C+3..C+K, C) in
-// pairs (the last one alone when their count is odd), with H(C+4) and P(C+4)
-// after the first pair (their last terms use that pair's tiles).
-__host__ __device__ __forceinline__ unsigned off_pairs(int K) { return K >= 3 ? (unsigned)(K - 1) / 2u : 0u; }
+// Ticket order: 0 = spine; then per column C the tile O(C+3, C) alone (the
+// one the spine takes two steps later, and the head of the chain of tiles
+// the helpers hand to each other: a task of its own has half the work per
+// term of a pair, so it keeps up sooner), the tiles O(C+4..C+K, C) in pairs
+// (the last one alone when their count is odd), with H(C+4) and P(C+4) after
+// the first pair (their last terms use the tiles C+3 and C+4).
+__host__ __device__ __forceinline__ unsigned off_pairs(int K) { return K >= 4 ? (unsigned)(K - 2) / 2u : 0u; }
 __host__ __device__ __forceinline__ unsigned tickets_per_column(int K) {
-  return off_pairs(K) + (K >= 4 ? 2u : 0u);
+  return (K >= 3 ? 1u : 0u) + off_pairs(K) + (K >= 4 ? 2u : 0u);
 }
 
 // kind 1: tile (R, C); kind 3: tiles (R, C) and (R+1, C); kind 2: H(R); kind 4: P(R).
@@ -1301,21 +1304,20 @@ __device__ __forceinline__ void decode(const Args<F>& A, unsigned t, int& kind, 
   const unsigned u = t - 1;
   C = u / per;
   unsigned k = u % per;
-  const unsigned np = off_pairs(A.K);
-  unsigned pair = 0;
-  if (np >= 1) {
-    if (k == 0) goto off;
-    --k;
-    pair = 1;
+  if (k == 0) {  // K >= 3 whenever there are tickets
+    kind = 1;
+    R = C + 3;
+    return;
   }
-  if (A.K >= 4) {
+  --k;  // from here K >= 4
+  unsigned pair = 0;
+  if (k >= 1) {
+    --k;
     if (k == 0) { kind = 2; R = C + 4; return; }
     if (k == 1) { kind = 4; R = C + 4; return; }
-    k -= 2;
+    pair = k - 1;
   }
-  pair += k;
-off:
-  R = C + 3 + 2 * (int64_t)pair;
+  R = C + 4 + 2 * (int64_t)pair;
   kind = (R + 1 <= C + A.K && R + 1 < A.NB) ? 3 : 1;
 }
 
