@@ -156,12 +156,9 @@ __device__ __forceinline__ bool wave_wait(const glb_i* f, const Ws<F>& w) {
   return true;
 }
 
-// Up to four flags (null: none) polled in one round trip; bounded like wave_wait.
+// One flag per lane (null: none), all polled in one round trip; bounded like wave_wait.
 template <typename F>
-__device__ __forceinline__ bool wave_wait4(const glb_i* f0, const glb_i* f1, const glb_i* f2, const glb_i* f3,
-                                           const Ws<F>& w) {
-  const int lane = lane_id();
-  const glb_i* mine = lane == 0 ? f0 : lane == 1 ? f1 : lane == 2 ? f2 : lane == 3 ? f3 : nullptr;
+__device__ __forceinline__ bool wave_wait_lanes(const glb_i* mine, const Ws<F>& w) {
   long long spins = 0;
   for (;;) {
     int v = 1;
@@ -178,6 +175,14 @@ __device__ __forceinline__ bool wave_wait4(const glb_i* f0, const glb_i* f1, con
   }
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   return true;
+}
+
+// Up to four flags (null: none), in lanes 0-3.
+template <typename F>
+__device__ __forceinline__ bool wave_wait4(const glb_i* f0, const glb_i* f1, const glb_i* f2, const glb_i* f3,
+                                           const Ws<F>& w) {
+  const int lane = lane_id();
+  return wave_wait_lanes<F>(lane == 0 ? f0 : lane == 1 ? f1 : lane == 2 ? f2 : lane == 3 ? f3 : nullptr, w);
 }
 
 template <typename F>
@@ -302,9 +307,13 @@ __device__ __forceinline__ bool apply_terms(const Args<F>& A, int64_t R, int64_t
     int64_t u = s;
     for (; u + 1 < e; u += 2) {
       acc = term_apply(x0, y0, acc);
+      __builtin_amdgcn_sched_barrier(0);
       term_load(A, R, C, u + 2 < e ? u + 2 : e - 1, bi, bj, x0, y0);
+      __builtin_amdgcn_sched_barrier(0);
       acc = term_apply(x1, y1, acc);
+      __builtin_amdgcn_sched_barrier(0);
       term_load(A, R, C, u + 3 < e ? u + 3 : e - 1, bi, bj, x1, y1);
+      __builtin_amdgcn_sched_barrier(0);
     }
     if (u < e) acc = term_apply(x0, y0, acc);
     s = e;
@@ -407,12 +416,16 @@ __device__ __forceinline__ bool apply_terms2(const Args<F>& A, int64_t R, int64_
     for (; u + 1 < e; u += 2) {
       acc0 = term_apply(a0, y0, acc0);
       acc1 = term_apply(b0, y0, acc1);
+      __builtin_amdgcn_sched_barrier(0);
       term_load(A, R, C, u + 2 < e ? u + 2 : e - 1, bi, bj, a0, y0);
       term_load_x(A, R + 1, u + 2 < e ? u + 2 : e - 1, bi, b0);
+      __builtin_amdgcn_sched_barrier(0);
       acc0 = term_apply(a1, y1, acc0);
       acc1 = term_apply(b1, y1, acc1);
+      __builtin_amdgcn_sched_barrier(0);
       term_load(A, R, C, u + 3 < e ? u + 3 : e - 1, bi, bj, a1, y1);
       term_load_x(A, R + 1, u + 3 < e ? u + 3 : e - 1, bi, b1);
+      __builtin_amdgcn_sched_barrier(0);
     }
     if (u < e) {
       acc0 = term_apply(a0, y0, acc0);
@@ -451,6 +464,162 @@ __device__ __attribute__((noinline)) void task_off2(const Args<F>& A_, int64_t R
     raise_flag(&A.w.tflag[tidx(A, R, C)]);
     raise_flag(&A.w.tflag[tidx(A, R + 1, C)]);
   }
+}
+
+// Four tiles of one column, O(R0 .. R0+3, C), one per wave (a strip; rows
+// past the band or the matrix are absent).  The terms' operands come through
+// LDS: per term the workgroup loads the strip's rows of band column block s,
+// L(R0..R0+3, s) (in each band column one contiguous run of 4T elements), and
+// L(C, s) once, and every wave reads its fragments there.  With operands in
+// registers each wave loads its own, so each element of a pair task's
+// operands crossed the CU's path to the L2 twice, in half-column pieces that
+// straddle cache lines; here once, in whole runs.  The next term's loads are
+// in flight while the current one is on the matrix cores.  Wave 0 finds each
+// run of published terms and hands its length to the others through LDS, so
+// that all waves take the same barriers.
+constexpr int SROWS = 4 * T;     // rows of a strip
+constexpr int SPX = SROWS + 16;  // LDS pitch of a strip column; 16 mod 32: the fragment reads
+constexpr int SPY = T + 16;      // and the L(C, s) pitch cover all banks twice, without conflicts
+constexpr int STRIP_D0 = 6;      // strips from the tile STRIP_D0 below the diagonal on (even, >= 6)
+constexpr int STRIP_MIN_K = 40;  // and only when K >= STRIP_MIN_K (>= STRIP_D0; below, pairs throughout)
+
+template <typename F>
+struct StripLoad {
+  F x[SROWS * T / NT];  // strip: element (r, c) with c = 2q + (wave >> 1), r = 64 (wave & 1) + lane
+  F y[T * T / NT];      // L(C, s): element (r, c) with c = 8q + 2 wave + (lane >> 5), r = lane & 31
+};
+
+template <typename F>
+__device__ __forceinline__ void strip_issue(const Args<F>& A, int64_t R0, int64_t C, int64_t s, StripLoad<F>& g) {
+  const int wave = wave_id(), lane = lane_id();
+  const RunT<F> x = band_run(A.a, R0 * T + 64 * (wave & 1) + lane, s * T + (wave >> 1), 2);
+  const RunT<F> y = band_run(A.a, C * T + (lane & 31), s * T + 2 * wave + (lane >> 5), 8);
+#pragma unroll
+  for (int q = 0; q < SROWS * T / NT; ++q) g.x[q] = aload<F>(opaque_ptr(x.in(q) ? x.at(q) : A.w.zero));
+#pragma unroll
+  for (int q = 0; q < T * T / NT; ++q) g.y[q] = aload<F>(opaque_ptr(y.in(q) ? y.at(q) : A.w.zero));
+}
+
+template <typename F>
+__device__ __forceinline__ void strip_put(lds_t<F>* xs, lds_t<F>* ys, const StripLoad<F>& g) {
+  const int wave = wave_id(), lane = lane_id();
+#pragma unroll
+  for (int q = 0; q < SROWS * T / NT; ++q) xs[(2 * q + (wave >> 1)) * SPX + 64 * (wave & 1) + lane] = g.x[q];
+#pragma unroll
+  for (int q = 0; q < T * T / NT; ++q) ys[(8 * q + 2 * wave + (lane >> 5)) * SPY + (lane & 31)] = g.y[q];
+}
+
+// acc[b] -= block (b & 1, b >> 1) of L(R0+wave, s) L(C, s)^T: four independent
+// chains.  The fragments of k-step q+1 are read while step q is on the matrix
+// cores (the scheduling barriers keep each read ahead of the steps before it).
+template <typename F>
+__device__ __forceinline__ void strip_apply(const lds_t<F>* xs, const lds_t<F>* ys, int wave, v4_t<F> (&acc)[4]) {
+  const int lane = lane_id();
+  const lds_t<F>* xw = xs + (lane >> 4) * SPX + T * wave + (lane & 15);
+  const lds_t<F>* yw = ys + (lane >> 4) * SPY + (lane & 15);
+  F f[2][4];
+  f[0][0] = xw[0], f[0][1] = xw[16], f[0][2] = yw[0], f[0][3] = yw[16];
+#pragma unroll
+  for (int q = 0; q < T / 4; ++q) {
+    const int c = q & 1, nx = c ^ 1;
+    if (q + 1 < T / 4) {
+      f[nx][0] = xw[4 * (q + 1) * SPX], f[nx][1] = xw[4 * (q + 1) * SPX + 16];
+      f[nx][2] = yw[4 * (q + 1) * SPY], f[nx][3] = yw[4 * (q + 1) * SPY + 16];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    acc[0] = mfma_xyt(-f[c][0], f[c][2], acc[0]);
+    acc[1] = mfma_xyt(-f[c][1], f[c][2], acc[1]);
+    acc[2] = mfma_xyt(-f[c][0], f[c][3], acc[2]);
+    acc[3] = mfma_xyt(-f[c][1], f[c][3], acc[3]);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// Whether every operand of term u is published (per lane).
+template <typename F>
+__device__ __forceinline__ int strip_ready(const Args<F>& A, int64_t R0, int64_t C, int64_t u) {
+  int f = __hip_atomic_load(&A.w.tflag[tidx(A, C, u)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const int64_t R = R0 + w;
+    if (R < A.NB && R - u <= A.K)
+      f &= __hip_atomic_load(&A.w.tflag[tidx(A, R, u)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  return f;
+}
+
+template <typename F>
+__device__ __attribute__((noinline)) void task_strip(const Args<F>& A_, int64_t R0_, int64_t C_, lds_t<F>* lds,
+                                                     lds_i* s_ok, lds_i* s_run) {
+  const Args<F> A = uniform(A_);
+  const int64_t R0 = uni(R0_), C = uni(C_);
+  const int wave = wave_id(), lane = lane_id();
+  const int64_t R = R0 + wave;
+  const bool mine = R < A.NB && R - C <= A.K;
+  v4_t<F> acc[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) acc[b] = blk_issue<F>(A, nullptr, R, C, b & 1, b >> 1);
+  lds_t<F>* xs = lds;
+  lds_t<F>* ys = lds + T * SPX;
+  int ok = 1;
+  int64_t s = R0 - A.K > 0 ? R0 - A.K : 0;
+  StripLoad<F> g;
+  while (s < C) {
+    if (wave == 0) {
+      const int span = C - s < 16 ? (int)(C - s) : 16;
+      const int f = lane < span ? strip_ready(A, R0, C, s + lane) : 1;
+      const unsigned long long bad = __ballot(lane < span && f == 0);
+      int e = bad ? (int)__builtin_ctzll(bad) : span;
+      if (e == 0) {
+        const glb_i* mine_f = nullptr;
+        if (lane == 0) mine_f = &A.w.tflag[tidx(A, C, s)];
+        else if (lane <= 4 && R0 + lane - 1 < A.NB && R0 + lane - 1 - s <= A.K)
+          mine_f = &A.w.tflag[tidx(A, R0 + lane - 1, s)];
+        e = wave_wait_lanes<F>(mine_f, A.w) ? 1 : -1;
+      }
+      if (lane == 0) *s_run = e;
+    }
+    __syncthreads();
+    const int e = uni(*s_run);
+    if (e < 0) {
+      ok = 0;
+      break;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");  // keeps the operand loads below the flags
+    strip_issue(A, R0, C, s, g);
+    wait_vmem();
+    strip_put(xs, ys, g);
+    __syncthreads();
+    for (int u = 0; u < e; ++u) {
+      const bool more = u + 1 < e;
+      if (more) strip_issue(A, R0, C, s + u + 1, g);
+      strip_apply(xs, ys, wave, acc);
+      __syncthreads();
+      if (more) {
+        wait_vmem();
+        strip_put(xs, ys, g);
+        __syncthreads();
+      }
+    }
+    s += e;
+  }
+  if (ok) ok = wave_wait(&A.w.tflag[tidx(A, C, C)], A.w) ? 1 : 0;
+  F yf0[T / 4], yf1[T / 4];
+  linvt_frags<F>(A.w.linvt + C * T * T, 0, yf0);
+  linvt_frags<F>(A.w.linvt + C * T * T, 1, yf1);
+  lds_t<F>* stage = lds + wave * T * LP;  // the term buffers are free: every wave passed the last term's barrier
+#pragma unroll
+  for (int b = 0; b < 4; ++b) blk_to_lds(stage, b & 1, b >> 1, acc[b]);
+  if (!ok && lane == 0) *s_ok = 0;
+  __syncthreads();
+  if (*s_ok == 0) return;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const v4_t<F> out = trsm_frags<F>(stage, (b >> 1) ? yf1 : yf0, b & 1, b >> 1);
+    if (mine) ablk_store(A.a, R, C, b & 1, b >> 1, out);
+  }
+  wait_vmem();
+  if (mine && lane == 0) raise_flag(&A.w.tflag[tidx(A, R, C)]);
 }
 
 // H(m): the tiles (m, m-1) and (m, m) the spine completes at step m-1, summed
@@ -520,9 +689,13 @@ __device__ __attribute__((noinline)) void task_pre(const Args<F>& A_, int64_t m,
     int64_t u = s;
     for (; u + 1 < e; u += 2) {
       pre_apply(o0, bi, di, dj, acc, accd);
+      __builtin_amdgcn_sched_barrier(0);
       pre_load(A, m, u + 2 < e ? u + 2 : e - 1, bj, o0);
+      __builtin_amdgcn_sched_barrier(0);
       pre_apply(o1, bi, di, dj, acc, accd);
+      __builtin_amdgcn_sched_barrier(0);
       pre_load(A, m, u + 3 < e ? u + 3 : e - 1, bj, o1);
+      __builtin_amdgcn_sched_barrier(0);
     }
     if (u < e) pre_apply(o0, bi, di, dj, acc, accd);
     s = e;
@@ -1289,15 +1462,18 @@ __device__ void spine(const Args<F>& A, lds_t<F>* base, lds_i* s_fail, lds_i* s_
 // Ticket order: 0 = spine; then per column C the tile O(C+3, C) alone (the
 // one the spine takes two steps later, and the head of the chain of tiles
 // the helpers hand to each other: a task of its own has half the work per
-// term of a pair, so it keeps up sooner), the tiles O(C+4..C+K, C) in pairs
-// (the last one alone when their count is odd), with H(C+4) and P(C+4) after
-// the first pair (their last terms use the tiles C+3 and C+4).
+// term of a pair, so it keeps up sooner), then the pair O(C+4, C), O(C+5, C),
+// H(C+4) and P(C+4) (their last terms use the tiles C+3 and C+4), then the
+// tiles O(C+6..C+K, C): in strips of four from K = STRIP_MIN_K on, else in
+// pairs (the last one alone when their count is odd).
 __host__ __device__ __forceinline__ unsigned off_pairs(int K) { return K >= 4 ? (unsigned)(K - 2) / 2u : 0u; }
 __host__ __device__ __forceinline__ unsigned tickets_per_column(int K) {
+  if (K >= STRIP_MIN_K) return 4u + (STRIP_D0 - 6) / 2 + (unsigned)(K - STRIP_D0 + 4) / 4u;
   return (K >= 3 ? 1u : 0u) + off_pairs(K) + (K >= 4 ? 2u : 0u);
 }
 
-// kind 1: tile (R, C); kind 3: tiles (R, C) and (R+1, C); kind 2: H(R); kind 4: P(R).
+// kind 1: tile (R, C); kind 3: tiles (R, C) and (R+1, C); kind 2: H(R); kind 4: P(R);
+// kind 5: the strip of tiles (R .. R+3, C).
 template <typename F>
 __device__ __forceinline__ void decode(const Args<F>& A, unsigned t, int& kind, int64_t& R, int64_t& C) {
   const unsigned per = tickets_per_column(A.K);
@@ -1310,6 +1486,15 @@ __device__ __forceinline__ void decode(const Args<F>& A, unsigned t, int& kind, 
     return;
   }
   --k;  // from here K >= 4
+  if (A.K >= STRIP_MIN_K) {
+    if (k == 1) { kind = 2; R = C + 4; return; }
+    if (k == 2) { kind = 4; R = C + 4; return; }
+    constexpr unsigned mid = (STRIP_D0 - 6) / 2;  // pairs between the first pair and the strips
+    if (k >= 3 + mid) { kind = 5; R = C + STRIP_D0 + 4 * (int64_t)(k - 3 - mid); return; }
+    R = k == 0 ? C + 4 : C + 6 + 2 * (int64_t)(k - 3);
+    kind = (R + 1 < A.NB) ? 3 : 1;  // R + 1 <= C + STRIP_D0 - 1 <= C + K
+    return;
+  }
   unsigned pair = 0;
   if (k >= 1) {
     --k;
@@ -1350,6 +1535,7 @@ __global__ void __launch_bounds__(NT, 2) factor2_kernel(Args<F> A) {
       if (R < A.NB) {
         if (kind == 1) task_off<F>(A, R, C, (lds_t<F>*)lds, (lds_i*)&s_ok);
         else if (kind == 3) task_off2<F>(A, R, C, (lds_t<F>*)lds, (lds_i*)&s_ok);
+        else if (kind == 5) task_strip<F>(A, R, C, (lds_t<F>*)lds, (lds_i*)&s_ok, (lds_i*)s_sync);
         else if (kind == 2) task_pre(A, R, (lds_i*)&s_ok);
         else task_p(A, R, (lds_i*)&s_ok);
       }

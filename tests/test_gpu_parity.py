@@ -100,15 +100,16 @@ def test_nonspd_info_matches_oracle(m, dval):
     assert info == m + 1 == oracle.factor(a, k)[1]
 
 
-@pytest.mark.parametrize("k", [180, 300])
+@pytest.mark.parametrize("k", [180, 300, 1300])
 @pytest.mark.parametrize("m", [0, 33, 700, 2047])
 def test_nonspd_info_with_helpers(k, m):
-    """A failing pivot while helper workgroups are at work (K = 6 and 10): the
-    first failing column is reported as the oracle reports it, and every
-    waiting workgroup leaves through the abort flag (the call returns within the
+    """A failing pivot while helper workgroups are at work (K = 6, 10, and 41,
+    where strips of four tiles wait at their shared barriers): the first
+    failing column is reported as the oracle reports it, and every waiting
+    workgroup leaves through the abort flag (the call returns within the
     test's time limit, far below the waits' own bound)."""
     import time
-    n = 2048
+    n = 2048 if k < 1000 else 2900
     l0 = synth.int_factor(n, k, 77 + k)
     dvec = np.ones(n)
     dvec[m] = -1.0
@@ -185,6 +186,27 @@ def test_tile_schedule_each_K(K):
             ab = synth.band_diagdom(n, k, 7 * n + K)
             check_against_oracle(ab, k, nrhs=1, seed=K)
             l0 = synth.int_factor(n, k, 11 + K, pow2_max=1)
+            l_gpu, info = gpu_factor(synth.band_ldlt(l0, k), k)
+            assert info == 0 and np.array_equal(l_gpu, l0), (n, k)
+    finally:
+        bc.set_walk_limit(prev)
+
+
+@pytest.mark.parametrize("K", [40, 41, 42, 43])
+def test_tile_schedule_strips(K):
+    """From K = 40 on the helpers take the tiles six or more below the
+    diagonal in strips of four (operands staged in LDS): every count of tiles
+    left for the last strip (K - 5 rows: 3, 0, 1, 2 past whole strips), n
+    ragged, with few tile rows past K (strips running into the matrix's end)
+    and with more; the integer factor must come out bit for bit."""
+    import paper_2305_04635_amd as bc
+    prev = bc.set_walk_limit(0)
+    try:
+        k = 32 * K - 5
+        for n in (32 * (K + 2) + 7, 32 * (K + 14) - 3):
+            ab = synth.band_diagdom(n, k, 13 * n + K)
+            check_against_oracle(ab, k, nrhs=1, seed=K)
+            l0 = synth.int_factor(n, k, 19 + K, pow2_max=1)
             l_gpu, info = gpu_factor(synth.band_ldlt(l0, k), k)
             assert info == 0 and np.array_equal(l_gpu, l0), (n, k)
     finally:
