@@ -177,6 +177,39 @@ __device__ __forceinline__ bool wave_wait_lanes(const glb_i* mine, const Ws<F>& 
   return true;
 }
 
+// As wave_wait_lanes, with one more flag, `extra` (null: none), polled in
+// lane 63 in the same round trips: the first time it reads set, `seen` runs
+// (once) and the wait goes on for the others.  Lets a task pick up the
+// inverse it will need as soon as that is published, while it still waits
+// for its last operands.
+template <typename F, typename Seen>
+__device__ __forceinline__ bool wave_wait_lanes_or(const glb_i* mine, const glb_i* extra, Seen seen, const Ws<F>& w) {
+  const int lane = lane_id();
+  long long spins = 0;
+  for (;;) {
+    const glb_i* p = lane == 63 ? extra : mine;
+    int v = 1;
+    if (p) v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long z = __ballot(v == 0);
+    if (extra && !(z >> 63)) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      seen();
+      extra = nullptr;
+    }
+    if ((z & ~(1ull << 63)) == 0) break;
+    if ((++spins & 15) == 0) {  // as in wave_wait
+      if (aflag(w.abort_flag)) return false;
+      if (spins > SPIN_LIMIT) {
+        __hip_atomic_store(w.abort_flag, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return false;
+      }
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  return true;
+}
+
 // Up to four flags (null: none), in lanes 0-3.
 template <typename F>
 __device__ __forceinline__ bool wave_wait4(const glb_i* f0, const glb_i* f1, const glb_i* f2, const glb_i* f3,
@@ -279,10 +312,16 @@ __device__ __forceinline__ v4_t<F> term_apply(const F (&xf)[T / 4], const F (&yf
 // published terms the operands of the next term load while the current one
 // is on the matrix cores, both steps of each pair always taken (the last term
 // of the run stands in past its end) so that the wave's counter of
-// outstanding loads stays exact.  Xrow = R, Yrow = C.
-template <typename F>
+// outstanding loads stays exact.  Xrow = R, Yrow = C.  When the wave has to
+// wait for the operands of the last term, s1 - 1, it also polls `at_flag`
+// (null: not) and runs `at` once that is set (wave_wait_lanes_or).
+struct NoAt {
+  __device__ void operator()() const {}
+};
+
+template <typename F, typename At = NoAt>
 __device__ __forceinline__ bool apply_terms(const Args<F>& A, int64_t R, int64_t C, int64_t s0, int64_t s1, int bi, int bj,
-                                            v4_t<F>& acc) {
+                                            v4_t<F>& acc, const glb_i* at_flag = nullptr, At at = At()) {
   const int lane = lane_id();
   int64_t s = s0;
   while (s < s1) {
@@ -295,9 +334,12 @@ __device__ __forceinline__ bool apply_terms(const Args<F>& A, int64_t R, int64_t
     const unsigned long long bad = __ballot(lane < span && f == 0);
     int64_t e = s + (bad ? (int)__builtin_ctzll(bad) : span);
     if (e == s) {
-      if (!wave_wait4<F>(&A.w.tflag[tidx(A, R, s)], C != R ? &A.w.tflag[tidx(A, C, s)] : nullptr, nullptr, nullptr,
-                         A.w))
-        return false;
+      const glb_i* f0 = &A.w.tflag[tidx(A, R, s)];
+      const glb_i* f1 = C != R ? &A.w.tflag[tidx(A, C, s)] : nullptr;
+      const bool w = at_flag && s + 1 == s1
+                         ? wave_wait_lanes_or<F>(lane == 0 ? f0 : lane == 1 ? f1 : nullptr, at_flag, at, A.w)
+                         : wave_wait4<F>(f0, f1, nullptr, nullptr, A.w);
+      if (!w) return false;
       e = s + 1;
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");  // keeps the operand loads below the flags
@@ -363,10 +405,19 @@ __device__ __attribute__((noinline)) void task_off(const Args<F>& A_, int64_t R,
   const int bi = wave & 1, bj = wave >> 1;
   v4_t<F> acc = blk_issue<F>(A, nullptr, R, C, bi, bj);
   const int64_t s0 = R - A.K > 0 ? R - A.K : 0;
-  int ok = apply_terms(A, R, C, s0, C, bi, bj, acc) ? 1 : 0;
-  if (ok) ok = wave_wait(&A.w.tflag[tidx(A, C, C)], A.w) ? 1 : 0;
+  // when the inverse is published while the wave still waits for the last
+  // term's operands, its fragments load then, off the tail
   F yf[T / 4];
-  linvt_frags<F>(A.w.linvt + C * T * T, bj, yf);
+  bool got = false;
+  const glb_i* invf = &A.w.tflag[tidx(A, C, C)];
+  int ok = apply_terms(A, R, C, s0, C, bi, bj, acc, invf, [&]() {
+             linvt_frags<F>(A.w.linvt + C * T * T, bj, yf);
+             got = true;
+           }) ? 1 : 0;
+  if (!got) {
+    if (ok) ok = wave_wait(invf, A.w) ? 1 : 0;
+    linvt_frags<F>(A.w.linvt + C * T * T, bj, yf);
+  }
   blk_to_lds(stage, bi, bj, acc);
   if (!ok && lane_id() == 0) *s_ok = 0;
   __syncthreads();
@@ -383,9 +434,10 @@ __device__ __attribute__((noinline)) void task_off(const Args<F>& A_, int64_t R,
 // matrix-core work behind each round trip.  When R > K the first term,
 // s = R-K, lies outside the band of row R+1: that operand loads as zero and
 // its flag is not checked.  Same run structure as apply_terms.
-template <typename F>
+template <typename F, typename At = NoAt>
 __device__ __forceinline__ bool apply_terms2(const Args<F>& A, int64_t R, int64_t C, int64_t s0, int64_t s1, int bi,
-                                             int bj, v4_t<F>& acc0, v4_t<F>& acc1) {
+                                             int bj, v4_t<F>& acc0, v4_t<F>& acc1, const glb_i* at_flag = nullptr,
+                                             At at = At()) {
   const int lane = lane_id();
   const int64_t s_in1 = R + 1 - A.K;   // first term inside the band for row R+1
   int64_t s = s0;
@@ -401,9 +453,14 @@ __device__ __forceinline__ bool apply_terms2(const Args<F>& A, int64_t R, int64_
     const unsigned long long bad = __ballot(lane < span && f == 0);
     int64_t e = s + (bad ? (int)__builtin_ctzll(bad) : span);
     if (e == s) {
-      if (!wave_wait4<F>(&A.w.tflag[tidx(A, R, s)], &A.w.tflag[tidx(A, C, s)],
-                         s >= s_in1 ? &A.w.tflag[tidx(A, R + 1, s)] : nullptr, nullptr, A.w))
-        return false;
+      const glb_i* f0 = &A.w.tflag[tidx(A, R, s)];
+      const glb_i* f1 = &A.w.tflag[tidx(A, C, s)];
+      const glb_i* f2 = s >= s_in1 ? &A.w.tflag[tidx(A, R + 1, s)] : nullptr;
+      const bool w = at_flag && s + 1 == s1
+                         ? wave_wait_lanes_or<F>(lane == 0 ? f0 : lane == 1 ? f1 : lane == 2 ? f2 : nullptr, at_flag,
+                                                 at, A.w)
+                         : wave_wait4<F>(f0, f1, f2, nullptr, A.w);
+      if (!w) return false;
       e = s + 1;
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");  // keeps the operand loads below the flags
@@ -445,10 +502,27 @@ __device__ __attribute__((noinline)) void task_off2(const Args<F>& A_, int64_t R
   v4_t<F> acc0 = blk_issue<F>(A, nullptr, R, C, bi, bj);
   v4_t<F> acc1 = blk_issue<F>(A, nullptr, R + 1, C, bi, bj);
   const int64_t s0 = R - A.K > 0 ? R - A.K : 0;
-  int ok = apply_terms2(A, R, C, s0, C, bi, bj, acc0, acc1) ? 1 : 0;
-  if (ok) ok = wave_wait(&A.w.tflag[tidx(A, C, C)], A.w) ? 1 : 0;
-  F yf[T / 4];  // one read of the inverse for both tiles
-  linvt_frags<F>(A.w.linvt + C * T * T, bj, yf);
+  // one read of the inverse for both tiles; picked up early as in task_off,
+  // then parked in this wave's LDS slot (in registers it would be live
+  // through the last term's loop, which has none to spare)
+  lds_t<F>* park = stage + 2 * T * LP + wave * (T / 4) * 64 + lane_id();
+  bool got = false;
+  const glb_i* invf = &A.w.tflag[tidx(A, C, C)];
+  int ok = apply_terms2(A, R, C, s0, C, bi, bj, acc0, acc1, invf, [&]() {
+             F t[T / 4];
+             linvt_frags<F>(A.w.linvt + C * T * T, bj, t);
+#pragma unroll
+             for (int q = 0; q < T / 4; ++q) park[64 * q] = t[q];
+             got = true;
+           }) ? 1 : 0;
+  F yf[T / 4];
+  if (got) {
+#pragma unroll
+    for (int q = 0; q < T / 4; ++q) yf[q] = park[64 * q];
+  } else {
+    if (ok) ok = wave_wait(invf, A.w) ? 1 : 0;
+    linvt_frags<F>(A.w.linvt + C * T * T, bj, yf);
+  }
   blk_to_lds(stage, bi, bj, acc0);
   blk_to_lds(stage + T * LP, bi, bj, acc1);
   if (!ok && lane_id() == 0) *s_ok = 0;
@@ -548,6 +622,26 @@ __device__ __forceinline__ int strip_ready(const Args<F>& A, int64_t R0, int64_t
   return f;
 }
 
+// L(C,C)^{-T} (column-major in global memory) into LDS, pitch LP, by one wave.
+template <typename F>
+__device__ __forceinline__ void linvt_to_lds(const glb_t<F>* linvt_g, lds_t<F>* lt) {
+  const int lane = lane_id();
+  F v[T * T / 64];
+#pragma unroll
+  for (int q = 0; q < T * T / 64; ++q) v[q] = aload<F>(linvt_g + 64 * q + lane);
+#pragma unroll
+  for (int q = 0; q < T * T / 64; ++q) lt[(2 * q + (lane >> 5)) * LP + (lane & 31)] = v[q];
+}
+
+// linvt_frags from the LDS copy.
+template <typename F>
+__device__ __forceinline__ void linvt_frags_lds(const lds_t<F>* lt, int bj, F (&yf)[T / 4]) {
+  const int lane = lane_id();
+  const int qmax = 4 * bj + 4;
+#pragma unroll
+  for (int q = 0; q < T / 4; ++q) yf[q] = (q < qmax) ? lt[(16 * bj + (lane & 15)) * LP + 4 * q + (lane >> 4)] : F(0);
+}
+
 template <typename F>
 __device__ __attribute__((noinline)) void task_strip(const Args<F>& A_, int64_t R0_, int64_t C_, lds_t<F>* lds,
                                                      lds_i* s_ok, lds_i* s_run) {
@@ -560,8 +654,10 @@ __device__ __attribute__((noinline)) void task_strip(const Args<F>& A_, int64_t 
 #pragma unroll
   for (int b = 0; b < 4; ++b) acc[b] = blk_issue<F>(A, nullptr, R, C, b & 1, b >> 1);
   lds_t<F>* xs = lds;
-  lds_t<F>* ys = lds + T * SPX;
-  int ok = 1;
+  lds_t<F>* ys = xs + T * SPX;
+  lds_t<F>* lt = ys + T * SPY;  // L(C,C)^{-T}, when wave 0 picked it up while waiting for the last term
+  const glb_i* invf = &A.w.tflag[tidx(A, C, C)];
+  int ok = 1, parked = 0;
   int64_t s = R0 - A.K > 0 ? R0 - A.K : 0;
   StripLoad<F> g;
   while (s < C) {
@@ -570,17 +666,26 @@ __device__ __attribute__((noinline)) void task_strip(const Args<F>& A_, int64_t 
       const int f = lane < span ? strip_ready(A, R0, C, s + lane) : 1;
       const unsigned long long bad = __ballot(lane < span && f == 0);
       int e = bad ? (int)__builtin_ctzll(bad) : span;
+      int park = 0;
       if (e == 0) {
         const glb_i* mine_f = nullptr;
         if (lane == 0) mine_f = &A.w.tflag[tidx(A, C, s)];
         else if (lane <= 4 && R0 + lane - 1 < A.NB && R0 + lane - 1 - s <= A.K)
           mine_f = &A.w.tflag[tidx(A, R0 + lane - 1, s)];
-        e = wave_wait_lanes<F>(mine_f, A.w) ? 1 : -1;
+        // waiting for the last term, whose operands come after the inverse
+        // as a rule: pick up the inverse meanwhile
+        const bool w = s + 1 == C ? wave_wait_lanes_or<F>(mine_f, invf, [&]() {
+                                      linvt_to_lds<F>(A.w.linvt + C * T * T, lt);
+                                      park = 1;
+                                    }, A.w)
+                                  : wave_wait_lanes<F>(mine_f, A.w);
+        e = w ? 1 : -1;
       }
-      if (lane == 0) *s_run = e;
+      if (lane == 0) s_run[0] = e, s_run[1] = park;
     }
     __syncthreads();
-    const int e = uni(*s_run);
+    const int e = uni(s_run[0]);
+    parked = uni(s_run[1]);
     if (e < 0) {
       ok = 0;
       break;
@@ -603,10 +708,15 @@ __device__ __attribute__((noinline)) void task_strip(const Args<F>& A_, int64_t 
     }
     s += e;
   }
-  if (ok) ok = wave_wait(&A.w.tflag[tidx(A, C, C)], A.w) ? 1 : 0;
   F yf0[T / 4], yf1[T / 4];
-  linvt_frags<F>(A.w.linvt + C * T * T, 0, yf0);
-  linvt_frags<F>(A.w.linvt + C * T * T, 1, yf1);
+  if (parked) {
+    linvt_frags_lds<F>(lt, 0, yf0);
+    linvt_frags_lds<F>(lt, 1, yf1);
+  } else {
+    if (ok) ok = wave_wait(invf, A.w) ? 1 : 0;
+    linvt_frags<F>(A.w.linvt + C * T * T, 0, yf0);
+    linvt_frags<F>(A.w.linvt + C * T * T, 1, yf1);
+  }
   lds_t<F>* stage = lds + wave * T * LP;  // the term buffers are free: every wave passed the last term's barrier
 #pragma unroll
   for (int b = 0; b < 4; ++b) blk_to_lds(stage, b & 1, b >> 1, acc[b]);
