@@ -622,26 +622,11 @@ __device__ __forceinline__ int strip_ready(const Args<F>& A, int64_t R0, int64_t
   return f;
 }
 
-// L(C,C)^{-T} (column-major in global memory) into LDS, pitch LP, by one wave.
-template <typename F>
-__device__ __forceinline__ void linvt_to_lds(const glb_t<F>* linvt_g, lds_t<F>* lt) {
-  const int lane = lane_id();
-  F v[T * T / 64];
-#pragma unroll
-  for (int q = 0; q < T * T / 64; ++q) v[q] = aload<F>(linvt_g + 64 * q + lane);
-#pragma unroll
-  for (int q = 0; q < T * T / 64; ++q) lt[(2 * q + (lane >> 5)) * LP + (lane & 31)] = v[q];
-}
-
-// linvt_frags from the LDS copy.
-template <typename F>
-__device__ __forceinline__ void linvt_frags_lds(const lds_t<F>* lt, int bj, F (&yf)[T / 4]) {
-  const int lane = lane_id();
-  const int qmax = 4 * bj + 4;
-#pragma unroll
-  for (int q = 0; q < T / 4; ++q) yf[q] = (q < qmax) ? lt[(16 * bj + (lane & 15)) * LP + 4 * q + (lane >> 4)] : F(0);
-}
-
+// The last term (s = C-1) is not taken through LDS: its operands L(R0.., C-1)
+// are the last to be published (by the previous column's strips), so each
+// wave waits for its own tile's operands only, loads its fragments itself,
+// picks up the inverse meanwhile when that comes first, and publishes its tile
+// without waiting for the other three.
 template <typename F>
 __device__ __attribute__((noinline)) void task_strip(const Args<F>& A_, int64_t R0_, int64_t C_, lds_t<F>* lds,
                                                      lds_i* s_ok, lds_i* s_run) {
@@ -655,37 +640,29 @@ __device__ __attribute__((noinline)) void task_strip(const Args<F>& A_, int64_t 
   for (int b = 0; b < 4; ++b) acc[b] = blk_issue<F>(A, nullptr, R, C, b & 1, b >> 1);
   lds_t<F>* xs = lds;
   lds_t<F>* ys = xs + T * SPX;
-  lds_t<F>* lt = ys + T * SPY;  // L(C,C)^{-T}, when wave 0 picked it up while waiting for the last term
   const glb_i* invf = &A.w.tflag[tidx(A, C, C)];
-  int ok = 1, parked = 0;
-  int64_t s = R0 - A.K > 0 ? R0 - A.K : 0;
+  int ok = 1;
+  const int64_t s_lo = R0 - A.K > 0 ? R0 - A.K : 0;
+  const int64_t s_end = s_lo < C ? C - 1 : C;  // the terms through LDS: [s_lo, s_end)
+  int64_t s = s_lo;
   StripLoad<F> g;
-  while (s < C) {
+  while (s < s_end) {
     if (wave == 0) {
-      const int span = C - s < 16 ? (int)(C - s) : 16;
+      const int span = s_end - s < 16 ? (int)(s_end - s) : 16;
       const int f = lane < span ? strip_ready(A, R0, C, s + lane) : 1;
       const unsigned long long bad = __ballot(lane < span && f == 0);
       int e = bad ? (int)__builtin_ctzll(bad) : span;
-      int park = 0;
       if (e == 0) {
         const glb_i* mine_f = nullptr;
         if (lane == 0) mine_f = &A.w.tflag[tidx(A, C, s)];
         else if (lane <= 4 && R0 + lane - 1 < A.NB && R0 + lane - 1 - s <= A.K)
           mine_f = &A.w.tflag[tidx(A, R0 + lane - 1, s)];
-        // waiting for the last term, whose operands come after the inverse
-        // as a rule: pick up the inverse meanwhile
-        const bool w = s + 1 == C ? wave_wait_lanes_or<F>(mine_f, invf, [&]() {
-                                      linvt_to_lds<F>(A.w.linvt + C * T * T, lt);
-                                      park = 1;
-                                    }, A.w)
-                                  : wave_wait_lanes<F>(mine_f, A.w);
-        e = w ? 1 : -1;
+        e = wave_wait_lanes<F>(mine_f, A.w) ? 1 : -1;
       }
-      if (lane == 0) s_run[0] = e, s_run[1] = park;
+      if (lane == 0) *s_run = e;
     }
     __syncthreads();
-    const int e = uni(s_run[0]);
-    parked = uni(s_run[1]);
+    const int e = uni(*s_run);
     if (e < 0) {
       ok = 0;
       break;
@@ -708,28 +685,53 @@ __device__ __attribute__((noinline)) void task_strip(const Args<F>& A_, int64_t 
     }
     s += e;
   }
+  // From here on each wave goes alone: the LDS terms ended with a barrier, so
+  // no wave reads the term buffers any more, and each stages its tile in a
+  // region of its own.
   F yf0[T / 4], yf1[T / 4];
-  if (parked) {
-    linvt_frags_lds<F>(lt, 0, yf0);
-    linvt_frags_lds<F>(lt, 1, yf1);
-  } else {
+  bool got = false;
+  if (ok && mine && s_end < C) {
+    const int64_t sl = C - 1;
+    const glb_i* fy = &A.w.tflag[tidx(A, C, sl)];
+    const glb_i* fx = R - sl <= A.K ? &A.w.tflag[tidx(A, R, sl)] : nullptr;  // else L(R, C-1) is outside the band
+    ok = wave_wait_lanes_or<F>(lane == 0 ? fy : lane == 1 ? fx : nullptr, invf, [&]() {
+           linvt_frags<F>(A.w.linvt + C * T * T, 0, yf0);
+           linvt_frags<F>(A.w.linvt + C * T * T, 1, yf1);
+           got = true;
+         }, A.w) ? 1 : 0;
+    F x0[T / 4], x1[T / 4], y0[T / 4], y1[T / 4];
+    term_load_x(A, R, sl, 0, x0);
+    term_load_x(A, R, sl, 1, x1);
+    term_load_x(A, C, sl, 0, y0);
+    term_load_x(A, C, sl, 1, y1);
+#pragma unroll
+    for (int q = 0; q < T / 4; ++q) {
+      acc[0] = mfma_xyt(-x0[q], y0[q], acc[0]);
+      acc[1] = mfma_xyt(-x1[q], y0[q], acc[1]);
+      acc[2] = mfma_xyt(-x0[q], y1[q], acc[2]);
+      acc[3] = mfma_xyt(-x1[q], y1[q], acc[3]);
+    }
+  }
+  if (!mine) return;
+  if (!got) {
     if (ok) ok = wave_wait(invf, A.w) ? 1 : 0;
     linvt_frags<F>(A.w.linvt + C * T * T, 0, yf0);
     linvt_frags<F>(A.w.linvt + C * T * T, 1, yf1);
   }
-  lds_t<F>* stage = lds + wave * T * LP;  // the term buffers are free: every wave passed the last term's barrier
+  if (!ok) {
+    if (lane == 0) *s_ok = 0;
+    return;
+  }
+  lds_t<F>* stage = lds + wave * T * LP;
 #pragma unroll
   for (int b = 0; b < 4; ++b) blk_to_lds(stage, b & 1, b >> 1, acc[b]);
-  if (!ok && lane == 0) *s_ok = 0;
-  __syncthreads();
-  if (*s_ok == 0) return;
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
     const v4_t<F> out = trsm_frags<F>(stage, (b >> 1) ? yf1 : yf0, b & 1, b >> 1);
-    if (mine) ablk_store(A.a, R, C, b & 1, b >> 1, out);
+    ablk_store(A.a, R, C, b & 1, b >> 1, out);
   }
   wait_vmem();
-  if (mine && lane == 0) raise_flag(&A.w.tflag[tidx(A, R, C)]);
+  if (lane == 0) raise_flag(&A.w.tflag[tidx(A, R, C)]);
 }
 
 // H(m): the tiles (m, m-1) and (m, m) the spine completes at step m-1, summed
