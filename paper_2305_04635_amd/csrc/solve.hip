@@ -209,10 +209,16 @@ template <int ST>
 __device__ __forceinline__ int ring_slot(int N) { return (N + ST + 1) % (ST + 1); }
 
 // Stores a result of row `row` (rhs p) where this lane has one (on), else
-// into the sink: the publication buffer (and, back, the solution).
-template <bool FWD>
+// into the sink: the publication buffer (and, back, the solution).  With
+// helpers (SH) the publication must be coherent across the chip (an
+// agent-scope store); without, only later launches read it, and a plain store
+// is enough (it leaves the L2 at the end of the kernel) and cheaper: the
+// spine's step at k = 100 took 17 % longer with the agent-scope stores.
+template <bool FWD, bool SH>
 __device__ __forceinline__ void publish(const SolveArgs& S, bool on, int64_t row, int p, double v) {
-  astore<double>((glb_d*)opaque(on ? S.pub + p * S.NBT + row : S.sink), v);
+  glb_d* dst = (glb_d*)opaque(on ? S.pub + p * S.NBT + row : S.sink);
+  if (SH) astore<double>(dst, v);
+  else *dst = v;
   if (!FWD) *(glb_d*)opaque(on && p < S.nrhs && row < S.a.n ? S.out + p * S.ldout + row : S.sink) = v;
 }
 
@@ -224,7 +230,7 @@ __device__ __forceinline__ void publish(const SolveArgs& S, bool on, int64_t row
 // through the step (not only in the lanes that need it), and every load and
 // store is issued on every path: otherwise the compiler cannot tell which
 // loads are still pending and waits for all of them before the reload.
-template <int ST, bool FWD>
+template <int ST, bool FWD, bool SH>
 __device__ __forceinline__ bool spine_step(const SolveArgs& S, int m, Stage<ST>& s, lds_d* ring, lds_d* tl,
                                            lds_i* s_fail) {
   const int tid = threadIdx.x, i = tid >> 3, p = tid & 7;
@@ -287,7 +293,7 @@ __device__ __forceinline__ bool spine_step(const SolveArgs& S, int m, Stage<ST>&
   }
   // The stores are made by every lane (the publication buffers have RHS_MAX
   // columns; masked-off lanes write the sink), for the reason given above.
-  publish<FWD>(S, direct, row, p, mine);
+  publish<FWD, SH>(S, direct, row, p, mine);
   __syncthreads();
   // Second half: the other rows take R u.
   mine = 0.0;
@@ -298,7 +304,7 @@ __device__ __forceinline__ bool spine_step(const SolveArgs& S, int m, Stage<ST>&
     mine = p == r ? acc : mine;
   } while (++r < S.nrhs);
   if (p < S.nrhs && !direct) yslot[p * SB + i] = mine;
-  publish<FWD>(S, !direct, row, p, mine);
+  publish<FWD, SH>(S, !direct, row, p, mine);
   load_d<ST, FWD>(S, b2, i, p, s);
   __syncthreads();
   return *s_fail == 0;
@@ -306,7 +312,7 @@ __device__ __forceinline__ bool spine_step(const SolveArgs& S, int m, Stage<ST>&
 
 // Inlined into the kernel: a call here costs more than the few registers the
 // kernel then spills (measured both ways).
-template <int ST, bool FWD>
+template <int ST, bool FWD, bool SH>
 __device__ __forceinline__ void spine(const SolveArgs& S, lds_d* ring, lds_d* tl, lds_i* s_fail) {
   const int tid = threadIdx.x, i = tid >> 3, p = tid & 7;
   for (int e = tid; e < (ST + 1) * SB * RHS_MAX; e += NT) ring[e] = 0.0;
@@ -322,10 +328,10 @@ __device__ __forceinline__ void spine(const SolveArgs& S, lds_d* ring, lds_d* tl
   // be copied at the loop's end, and the copy waits for the loads).
   int m = 0;
   for (; m + 1 < S.NB; m += 2) {
-    if (!spine_step<ST, FWD>(S, m, s0, ring, tl, s_fail)) return;
-    if (!spine_step<ST, FWD>(S, m + 1, s1, ring, tl, s_fail)) return;
+    if (!spine_step<ST, FWD, SH>(S, m, s0, ring, tl, s_fail)) return;
+    if (!spine_step<ST, FWD, SH>(S, m + 1, s1, ring, tl, s_fail)) return;
   }
-  if (m < S.NB) spine_step<ST, FWD>(S, m, s0, ring, tl, s_fail);
+  if (m < S.NB) spine_step<ST, FWD, SH>(S, m, s0, ring, tl, s_fail);
 }
 
 // Helper for block B: z_B = sum over the far neighbours N of L(B,N) y_N
@@ -411,7 +417,8 @@ __device__ __forceinline__ bool helper(const SolveArgs& S, int B, lds_i* s_flag)
 
 // ---------------------------------------------------------------- kernels
 
-template <int ST, bool FWD>
+// SH: there are helpers (they read the spine's results while the pass runs).
+template <int ST, bool FWD, bool SH>
 __global__ void __launch_bounds__(NT) solve_kernel(SolveArgs S) {
   __shared__ double ring[(ST + 1) * SB * RHS_MAX];
   __shared__ double tl[SB * RHS_MAX];
@@ -425,7 +432,7 @@ __global__ void __launch_bounds__(NT) solve_kernel(SolveArgs S) {
     __syncthreads();
     if (t > nhelp) break;
     if (t == 0) {
-      spine<ST, FWD>(S, (lds_d*)ring, (lds_d*)tl, (lds_i*)&s_flag);
+      spine<ST, FWD, SH>(S, (lds_d*)ring, (lds_d*)tl, (lds_i*)&s_flag);
     } else {
       // forward: B = ST+1 .. NB-1; back: B = NB-ST-2 .. 0
       const int B = FWD ? ST + t : S.NB - ST - 1 - t;
@@ -570,13 +577,13 @@ __global__ void __launch_bounds__(NT) prep_kernel(Band a, int NB, const glb_d* d
   }
 }
 
-template <int ST>
+template <int ST, bool SH>
 void launch_pair(const Band& a, const glb_d* dinvt, glb_d* ops, const SolveArgs& f, const SolveArgs& b, int grid,
                  hipStream_t st) {
   prep_kernel<ST, true><<<f.NB, NT, 0, st>>>(a, f.NB, dinvt, ops);
-  solve_kernel<ST, true><<<grid, NT, 0, st>>>(f);
+  solve_kernel<ST, true, SH><<<grid, NT, 0, st>>>(f);
   prep_kernel<ST, false><<<f.NB, NT, 0, st>>>(a, f.NB, dinvt, ops);
-  solve_kernel<ST, false><<<grid, NT, 0, st>>>(b);
+  solve_kernel<ST, false, SH><<<grid, NT, 0, st>>>(b);
 }
 
 // Blocks of the band the spine applies itself: all of them up to ST_MAX,
@@ -646,8 +653,9 @@ hipError_t bandchol_solve_launch(int64_t n, int64_t k, int64_t nrhs, const doubl
     const int64_t fg = (4 * len + 255) / 256;
     solve_fill_kernel<<<(unsigned)(fg < 2048 ? fg : 2048), 256, 0, st>>>(pubarea, len, (int64_t)stride, queues,
                                                                          abort_flag, zero, preset);
-    if (ST == 1) launch_pair<1>(a, dinvt, ops, F, Bk, grid, st);
-    else launch_pair<ST_MAX>(a, dinvt, ops, F, Bk, grid, st);
+    if (ST == 1) launch_pair<1, false>(a, dinvt, ops, F, Bk, grid, st);  // KS <= 1: never helpers
+    else if (nhelp == 0) launch_pair<ST_MAX, false>(a, dinvt, ops, F, Bk, grid, st);
+    else launch_pair<ST_MAX, true>(a, dinvt, ops, F, Bk, grid, st);
     if (d_status) solve_status_kernel<<<1, 1, 0, st>>>(abort_flag, d_status);
   }
   return hipGetLastError();
