@@ -20,7 +20,10 @@
 // waits for lower tickets or for spine steps:
 //   O(R, C), R - C >= 3: acc = A(R,C) - sum_s L(R,s) L(C,s)^T (terms applied as
 //            their operand tiles are published), then L(R,C) = acc L(C,C)^{-T};
-//            two tiles of one column share a task;
+//            the tile three below the diagonal alone, then two tiles of one
+//            column per task (operands in registers), or for wide bands, from
+//            six below the diagonal on, four per task with the operands staged
+//            once per workgroup in LDS;
 //   H(m):    the tiles (m, m-1) and (m, m) the spine completes at step m-1,
 //            summed over s <= m-4;
 //   P(m):    the tile (m, m-2) the spine completes at step m-1, summed over
