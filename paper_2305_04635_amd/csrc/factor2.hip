@@ -22,8 +22,8 @@
 //            their operand tiles are published), then L(R,C) = acc L(C,C)^{-T};
 //            the tile three below the diagonal alone, then two tiles of one
 //            column per task (operands in registers), or for wide bands, from
-//            six below the diagonal on, four per task with the operands staged
-//            once per workgroup in LDS;
+//            eight below the diagonal on, four per task with the operands
+//            staged once per workgroup in LDS;
 //   H(m):    the tiles (m, m-1) and (m, m) the spine completes at step m-1,
 //            summed over s <= m-4;
 //   P(m):    the tile (m, m-2) the spine completes at step m-1, summed over
@@ -557,7 +557,7 @@ __device__ __attribute__((noinline)) void task_off2(const Args<F>& A_, int64_t R
 constexpr int SROWS = 4 * T;     // rows of a strip
 constexpr int SPX = SROWS + 16;  // LDS pitch of a strip column; 16 mod 32: the fragment reads
 constexpr int SPY = T + 16;      // and the L(C, s) pitch cover all banks twice, without conflicts
-constexpr int STRIP_D0 = 6;      // strips from the tile STRIP_D0 below the diagonal on (even, >= 6)
+constexpr int STRIP_D0 = 8;      // strips from the tile STRIP_D0 below the diagonal on (even, >= 6)
 constexpr int STRIP_MIN_K = 40;  // and only when K >= STRIP_MIN_K (>= STRIP_D0; below, pairs throughout)
 
 template <typename F>
@@ -1579,8 +1579,9 @@ __device__ void spine(const Args<F>& A, lds_t<F>* base, lds_i* s_fail, lds_i* s_
 // the helpers hand to each other: a task of its own has half the work per
 // term of a pair, so it keeps up sooner), then the pair O(C+4, C), O(C+5, C),
 // H(C+4) and P(C+4) (their last terms use the tiles C+3 and C+4), then the
-// tiles O(C+6..C+K, C): in strips of four from K = STRIP_MIN_K on, else in
-// pairs (the last one alone when their count is odd).
+// tiles O(C+6..C+K, C) in pairs (the last one alone when their count is odd),
+// except that from K = STRIP_MIN_K on those from O(C+STRIP_D0, C) on go in
+// strips of four.
 __host__ __device__ __forceinline__ unsigned off_pairs(int K) { return K >= 4 ? (unsigned)(K - 2) / 2u : 0u; }
 __host__ __device__ __forceinline__ unsigned tickets_per_column(int K) {
   if (K >= STRIP_MIN_K) return 4u + (STRIP_D0 - 6) / 2 + (unsigned)(K - STRIP_D0 + 4) / 4u;

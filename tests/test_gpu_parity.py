@@ -194,9 +194,9 @@ def test_tile_schedule_each_K(K):
 
 @pytest.mark.parametrize("K", [40, 41, 42, 43])
 def test_tile_schedule_strips(K):
-    """From K = 40 on the helpers take the tiles six or more below the
+    """From K = 40 on the helpers take the tiles eight or more below the
     diagonal in strips of four (operands staged in LDS): every count of tiles
-    left for the last strip (K - 5 rows: 3, 0, 1, 2 past whole strips), n
+    left for the last strip (K - 7 rows: 1, 2, 3, 0 past whole strips), n
     ragged, with few tile rows past K (strips running into the matrix's end)
     and with more; the integer factor must come out bit for bit."""
     import paper_2305_04635_amd as bc
