@@ -558,7 +558,7 @@ constexpr int SROWS = 4 * T;     // rows of a strip
 constexpr int SPX = SROWS + 16;  // LDS pitch of a strip column; 16 mod 32: the fragment reads
 constexpr int SPY = T + 16;      // and the L(C, s) pitch cover all banks twice, without conflicts
 constexpr int STRIP_D0 = 8;      // strips from the tile STRIP_D0 below the diagonal on (even, >= 6)
-constexpr int STRIP_MIN_K = 40;  // and only when K >= STRIP_MIN_K (>= STRIP_D0; below, pairs throughout)
+constexpr int STRIP_MIN_K = 12;  // and only when K >= STRIP_MIN_K (>= STRIP_D0; below, pairs throughout)
 
 template <typename F>
 struct StripLoad {

@@ -42,7 +42,7 @@ def test_factor_f32_integer_exact(n, k):
     assert np.array_equal(l32.astype(np.float64), l0)
 
 
-@pytest.mark.parametrize("n,k", [(2000, 100), (1500, 96), (777, 200), (3001, 33), (2900, 1291)])
+@pytest.mark.parametrize("n,k", [(2000, 100), (1500, 96), (777, 200), (3001, 33), (1300, 420), (2900, 1291)])
 def test_factor_f32_matches_oracle(n, k):
     ab = synth.band_diagdom(n, k, 5 * n + k)
     l32, info = gpu_factor_f32(ab, k)

@@ -100,11 +100,11 @@ def test_nonspd_info_matches_oracle(m, dval):
     assert info == m + 1 == oracle.factor(a, k)[1]
 
 
-@pytest.mark.parametrize("k", [180, 300, 1300])
+@pytest.mark.parametrize("k", [180, 300, 500, 1300])
 @pytest.mark.parametrize("m", [0, 33, 700, 2047])
 def test_nonspd_info_with_helpers(k, m):
-    """A failing pivot while helper workgroups are at work (K = 6, 10, and 41,
-    where strips of four tiles wait at their shared barriers): the first
+    """A failing pivot while helper workgroups are at work (K = 6, 10, 16 and
+    41; from K = 12 on strips of four tiles wait at their shared barriers): the first
     failing column is reported as the oracle reports it, and every waiting
     workgroup leaves through the abort flag (the call returns within the
     test's time limit, far below the waits' own bound)."""
@@ -192,13 +192,14 @@ def test_tile_schedule_each_K(K):
         bc.set_walk_limit(prev)
 
 
-@pytest.mark.parametrize("K", [40, 41, 42, 43])
+@pytest.mark.parametrize("K", [12, 13, 14, 15, 40, 41, 42, 43])
 def test_tile_schedule_strips(K):
-    """From K = 40 on the helpers take the tiles eight or more below the
+    """From K = 12 on the helpers take the tiles eight or more below the
     diagonal in strips of four (operands staged in LDS): every count of tiles
-    left for the last strip (K - 7 rows: 1, 2, 3, 0 past whole strips), n
-    ragged, with few tile rows past K (strips running into the matrix's end)
-    and with more; the integer factor must come out bit for bit."""
+    left for the last strip (K - 7 rows: 1, 2, 3, 0 past whole strips), at
+    the smallest K and at wide bands, n ragged, with few tile rows past K
+    (strips running into the matrix's end) and with more; the integer factor
+    must come out bit for bit."""
     import paper_2305_04635_amd as bc
     prev = bc.set_walk_limit(0)
     try:
