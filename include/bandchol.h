@@ -186,7 +186,7 @@ int64_t bandchol_spine_profile(int64_t n, int64_t k, int64_t reps, double* out, 
  * The factor (FP64, FP32, and the wide systems of batch plans when the plan is
  * created) takes, in this order: the walk for K up to the walk limit
  * (bandchol_set_walk_limit; by default K = 0 only), the table entry of the
- * bucket, else the rule w = CUs/4 for K <= 16, CUs/2 for K <= 24, CUs for
+ * bucket, else the rule w = CUs/4 for K <= 11, CUs for
  * K <= 55, 2 x CUs above (at least 2).  The FP32 factor has no walk and takes
  * the rule where the choice is 1.  The table is process-wide and guarded by a mutex; it starts empty.
  *

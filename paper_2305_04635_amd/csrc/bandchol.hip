@@ -198,11 +198,14 @@ int n_bucket(int64_t n) {
 // tiles of a column, K + 1, each updated by up to K earlier columns), while
 // helpers beyond what the columns in flight can feed only contend with the
 // spine for memory and matrix cores.  Counts that spread evenly over the CUs
-// (a quarter, half, one or two workgroups per CU) measured better than those
+// (a quarter, one or two workgroups per CU) measured better than those
 // between them (n = 1e5, k = 1500: 27.7 ms with one per CU, 30.4 with 1.5).
+// From K = 12 on the far tiles go in strips of four, which want one
+// workgroup per CU (n = 1e5, k = 500, K = 16: 18.5 ms against 19.0 with a
+// quarter).
 int spine_rule(int K) {
   const int c = num_cus();
-  int g = K <= 16 ? c / 4 : K <= 24 ? c / 2 : K <= 55 ? c : 2 * c;
+  int g = K < 12 ? c / 4 : K <= 55 ? c : 2 * c;
   return g < 2 ? 2 : g;
 }
 

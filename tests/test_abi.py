@@ -122,13 +122,13 @@ def test_schedule_rule_and_table_on_host(tmp_path, monkeypatch):
     bc.tune_clear()
     prev = bc.set_walk_limit(0)
     try:
-        # rule: a quarter, half, one or two workgroups per CU (256 CUs) by K
+        # rule: a quarter, one or two workgroups per CU (256 CUs) by K
         assert bc.schedule(100000, 0) == 1            # diagonal: the walk
         assert bc.schedule(100000, 50) == 64          # K = 2
-        assert bc.schedule(100000, 500) == 64         # K = 16
-        assert bc.schedule(100000, 520) == 128        # K = 17
-        assert bc.schedule(100000, 768) == 128        # K = 24
-        assert bc.schedule(100000, 769) == 256        # K = 25
+        assert bc.schedule(100000, 352) == 64         # K = 11
+        assert bc.schedule(100000, 353) == 256        # K = 12
+        assert bc.schedule(100000, 500) == 256        # K = 16
+        assert bc.schedule(100000, 768) == 256        # K = 24
         assert bc.schedule(100000, 1000) == 256       # K = 32
         assert bc.schedule(100000, 1500) == 256       # K = 47
         assert bc.schedule(100000, 1760) == 256       # K = 55

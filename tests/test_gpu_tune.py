@@ -28,7 +28,7 @@ def candidates(bc, n, k):
     K = -(-kk // bc.tile())
     if K == 0:
         return {1}
-    rule = 64 if K <= 16 else 128 if K <= 24 else 256 if K <= 55 else 512
+    rule = 64 if K <= 11 else 256 if K <= 55 else 512
     return ({1} if K <= 15 else set()) | SPINE_COUNTS | {rule}
 
 
