@@ -417,8 +417,11 @@ __device__ __forceinline__ bool helper(const SolveArgs& S, int B, lds_i* s_flag)
 
 // ---------------------------------------------------------------- kernels
 
-// SH: there are helpers (they read the spine's results while the pass runs).
-template <int ST, bool FWD, bool SH>
+// HV: 0 = no helpers; else the helpers are sized for HV right-hand sides (1,
+// 2, 4 or 8, the pass's count rounded up) and read the spine's results while
+// the pass runs.  One helper variant per kernel: compiled together, the
+// widest set every kernel's register budget.
+template <int ST, bool FWD, int HV>
 __global__ void __launch_bounds__(NT) solve_kernel(SolveArgs S) {
   __shared__ double ring[(ST + 1) * SB * RHS_MAX];
   __shared__ double tl[SB * RHS_MAX];
@@ -432,16 +435,14 @@ __global__ void __launch_bounds__(NT) solve_kernel(SolveArgs S) {
     __syncthreads();
     if (t > nhelp) break;
     if (t == 0) {
-      spine<ST, FWD, SH>(S, (lds_d*)ring, (lds_d*)tl, (lds_i*)&s_flag);
+      spine<ST, FWD, (HV > 0)>(S, (lds_d*)ring, (lds_d*)tl, (lds_i*)&s_flag);
     } else {
-      // forward: B = ST+1 .. NB-1; back: B = NB-ST-2 .. 0
-      const int B = FWD ? ST + t : S.NB - ST - 1 - t;
-      // helpers sized to the pass's right-hand sides (the missing ones would read zeros)
-      const bool ok = S.nrhs == 1   ? helper<ST, FWD, 2, 1>(S, B, (lds_i*)&s_flag)
-                      : S.nrhs == 2 ? helper<ST, FWD, 2, 2>(S, B, (lds_i*)&s_flag)
-                      : S.nrhs <= 4 ? helper<ST, FWD, 1, 4>(S, B, (lds_i*)&s_flag)
-                                    : helper<ST, FWD, 1, RHS_MAX>(S, B, (lds_i*)&s_flag);
-      if (!ok) break;
+      if constexpr (HV > 0) {
+        // forward: B = ST+1 .. NB-1; back: B = NB-ST-2 .. 0
+        const int B = FWD ? ST + t : S.NB - ST - 1 - t;
+        // helpers sized to the pass's right-hand sides (the missing ones would read zeros)
+        if (!helper<ST, FWD, (HV <= 2 ? 2 : 1), HV>(S, B, (lds_i*)&s_flag)) break;
+      }
     }
     if (s_flag) break;
   }
@@ -577,13 +578,13 @@ __global__ void __launch_bounds__(NT) prep_kernel(Band a, int NB, const glb_d* d
   }
 }
 
-template <int ST, bool SH>
+template <int ST, int HV>
 void launch_pair(const Band& a, const glb_d* dinvt, glb_d* ops, const SolveArgs& f, const SolveArgs& b, int grid,
                  hipStream_t st) {
   prep_kernel<ST, true><<<f.NB, NT, 0, st>>>(a, f.NB, dinvt, ops);
-  solve_kernel<ST, true, SH><<<grid, NT, 0, st>>>(f);
+  solve_kernel<ST, true, HV><<<grid, NT, 0, st>>>(f);
   prep_kernel<ST, false><<<f.NB, NT, 0, st>>>(a, f.NB, dinvt, ops);
-  solve_kernel<ST, false, SH><<<grid, NT, 0, st>>>(b);
+  solve_kernel<ST, false, HV><<<grid, NT, 0, st>>>(b);
 }
 
 // Blocks of the band the spine applies itself: all of them up to ST_MAX,
@@ -653,9 +654,12 @@ hipError_t bandchol_solve_launch(int64_t n, int64_t k, int64_t nrhs, const doubl
     const int64_t fg = (4 * len + 255) / 256;
     solve_fill_kernel<<<(unsigned)(fg < 2048 ? fg : 2048), 256, 0, st>>>(pubarea, len, (int64_t)stride, queues,
                                                                          abort_flag, zero, preset);
-    if (ST == 1) launch_pair<1, false>(a, dinvt, ops, F, Bk, grid, st);  // KS <= 1: never helpers
-    else if (nhelp == 0) launch_pair<ST_MAX, false>(a, dinvt, ops, F, Bk, grid, st);
-    else launch_pair<ST_MAX, true>(a, dinvt, ops, F, Bk, grid, st);
+    if (ST == 1) launch_pair<1, 0>(a, dinvt, ops, F, Bk, grid, st);  // KS <= 1: never helpers
+    else if (nhelp == 0) launch_pair<ST_MAX, 0>(a, dinvt, ops, F, Bk, grid, st);
+    else if (nr == 1) launch_pair<ST_MAX, 1>(a, dinvt, ops, F, Bk, grid, st);
+    else if (nr == 2) launch_pair<ST_MAX, 2>(a, dinvt, ops, F, Bk, grid, st);
+    else if (nr <= 4) launch_pair<ST_MAX, 4>(a, dinvt, ops, F, Bk, grid, st);
+    else launch_pair<ST_MAX, RHS_MAX>(a, dinvt, ops, F, Bk, grid, st);
     if (d_status) solve_status_kernel<<<1, 1, 0, st>>>(abort_flag, d_status);
   }
   return hipGetLastError();
